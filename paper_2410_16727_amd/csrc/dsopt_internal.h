@@ -1,0 +1,111 @@
+// Device-side records shared by the host library and the gfx950 kernels.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+#include "dsopt.h"
+
+namespace dsk {
+
+constexpr int NJ = 7;
+constexpr int WAVE = 64;            // CDNA wavefront
+constexpr int WAVES_PER_BLOCK = 4;  // independent tiles per workgroup
+constexpr int BLOCK = WAVE * WAVES_PER_BLOCK;
+
+// Robot table, read with uniform (scalar) loads by every wavefront.
+struct RobotDev {
+  float F[7][12];        // fixed transform before joint i, 3x4 row-major
+  float Fee[12];
+  float qlo[7], qhi[7];
+  int32_t ns;
+  int32_t link_begin[8];             // spheres of link l (1..7): [link_begin[l-1], link_begin[l])
+  float4 sph[DS_MAX_SPHERES];        // offset xyz, radius; sorted by link
+  int32_t perm[DS_MAX_SPHERES];      // sorted position -> caller's sphere index
+};
+
+struct ParamsDev {
+  float wc, eps, inv_eps, half_inv_eps;
+  float lv, la, lj, wp, wr, wl;
+  float c1, delta0, dmax, dt, tol_pos, tol_rot;
+  int32_t m, nls, n_iters, block_iters;
+};
+
+// One resident scene: the 8 corners of cell (i,j,k) are the 32-byte record
+// i + (nx-1)*(j + (ny-1)*k): [c000 c100 c010 c110 | c001 c101 c011 c111].
+struct SceneDev {
+  const float4* rec;
+  int32_t nx, ny, nz;    // node counts
+  float ox, oy, oz, inv_h;
+  uint32_t bytes;        // size of the record array
+};
+
+struct ProbDev {
+  SceneDev sc;
+  float qs[7];
+  float pd[3];
+  float quat[4];         // goal quaternion as given (normalised in the kernel)
+  int32_t S, T, G;       // seeds, horizon, lanes per seed (16, 32 or 64)
+  int32_t n_iters;
+  const float* seeds;    // [S][T][7]
+  float* out_traj;       // [S][T][7] or null
+  float* final_traj;     // arena [S][T][7]
+  ds_seed_result* seed_res;   // arena [S]
+  ds_result* result;          // arena
+  float *tr_x, *tr_g, *tr_J, *tr_d, *tr_a;   // trace buffers or null
+};
+
+struct TileDev {
+  int32_t prob;          // index into the problem table
+  int32_t seed0;         // first seed of the tile
+  int32_t nseed;         // seeds in the tile (1..64/G)
+  int32_t G;
+  float* state;          // tile state (layout below)
+};
+
+// Tile state, float offsets; one column per lane.
+constexpr int ST_X = 0;                      // [7][64] iterate
+constexpr int ST_G = ST_X + NJ * WAVE;       // [7][64] gradient
+constexpr int ST_J = ST_G + NJ * WAVE;       // [64] cost (group-uniform)
+constexpr int ST_CNT = ST_J + WAVE;          // [64] history count (int)
+constexpr int ST_HEAD = ST_CNT + WAVE;       // [64] ring head (int)
+constexpr int ST_ITER = ST_HEAD + WAVE;      // [64] iterations done (int)
+constexpr int ST_EVC = ST_ITER + WAVE;       // [64] cost-only evaluations (int)
+constexpr int ST_EVG = ST_EVC + WAVE;        // [64] cost+gradient evaluations (int)
+constexpr int ST_RHO = ST_EVG + WAVE;        // [m][64] 1 / s^T y
+constexpr int ST_YY = ST_RHO + DS_MAX_HISTORY * WAVE;    // [m][64] y^T y
+constexpr int ST_S = ST_YY + DS_MAX_HISTORY * WAVE;      // [m][7][64]
+constexpr int ST_Y = ST_S + DS_MAX_HISTORY * NJ * WAVE;  // [m][7][64]
+constexpr int ST_FLOATS = ST_Y + DS_MAX_HISTORY * NJ * WAVE;
+constexpr size_t ST_BYTES = ((size_t)ST_FLOATS * 4 + 255) / 256 * 256;
+
+// Serving: one slot per admitted request.
+struct SlotDev {
+  int32_t active;        // 1 when the slot holds a request
+  int32_t prob;          // problem-table index of the request
+  int32_t tile0, ntiles; // its tiles in the tile table
+};
+
+}  // namespace dsk
+
+// Releases the serving state of a plan (dsopt_serve.cpp).
+void ds_serve_free(ds_plan* plan);
+
+// Launch wrappers (dsopt_kernels.hip).
+namespace dsk {
+hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* rec,
+                            hipStream_t s);
+hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
+                           const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
+                           int max_iters, hipStream_t s);
+hipError_t launch_best(const ProbDev* probs, int n_probs, hipStream_t s);
+hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
+                       const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
+                       int with_grad, hipStream_t s);
+hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
+                          hipStream_t s);
+hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
+hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
+                             const TileDev* tiles, const int* tile_list, int* counter,
+                             int max_tiles, int grid_blocks, int max_iters, hipStream_t s);
+}  // namespace dsk

@@ -1,0 +1,851 @@
+// gfx950 kernels of the seeded trajectory optimiser.
+//
+// Mapping: one wavefront owns one tile = 1, 2 or 4 seeds of one problem;
+// lane t of a seed's lane group holds waypoint t (group size G = 64, 32 or
+// 16 >= T).  Per lane the kernel runs the whole per-waypoint chain of the
+// objective (App. A.6): forward kinematics (sincos + 3x4 compositions with
+// the robot table read through the scalar cache), sphere centres, an ESDF
+// gather of one 32-byte corner record per sphere (two 16-byte buffer
+// loads), the smooth hinge, and -- for the gradient -- the joint-axis
+// adjoint: sphere forces f = w_c phi'(D) grad d accumulated per link into
+// a wrench and projected on every preceding joint twist, recomputing the
+// kinematics instead of storing transforms.  Finite differences of the
+// trajectory (smoothness) move between lanes with cross-lane shuffles;
+// per-seed sums (cost, L-BFGS dot products, Armijo tests) are butterfly
+// reductions inside the lane group, so every lane ends with bitwise the same
+// value and the reduction order depends only on G.  Nothing here is a dense
+// contraction: no MFMA.
+#include <hip/hip_runtime.h>
+
+#include <cfloat>
+#include <cmath>
+
+#include "dsopt_internal.h"
+
+namespace dsk {
+namespace {
+
+constexpr unsigned RSRC_DWORD3 = 0x00020000u;   // raw buffer, gfx9 family
+
+__device__ __forceinline__ float grp_sum(float v, int G) {
+  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off);
+  return v;
+}
+__device__ __forceinline__ float grp_max(float v, int G) {
+  for (int off = 1; off < G; off <<= 1) v = fmaxf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ float grp_min(float v, int G) {
+  for (int off = 1; off < G; off <<= 1) v = fminf(v, __shfl_xor(v, off));
+  return v;
+}
+__device__ __forceinline__ float dot7(const float* a, const float* b) {
+  float s = a[0] * b[0];
+#pragma unroll
+  for (int j = 1; j < NJ; ++j) s += a[j] * b[j];
+  return s;
+}
+
+struct Goal {
+  float pd[3];
+  float Rd[9];
+};
+
+// Unit goal quaternion (w, x, y, z) -> rotation matrix (uniform per tile).
+__device__ __forceinline__ Goal make_goal(const ProbDev& pb) {
+  Goal g;
+  float w = pb.quat[0], x = pb.quat[1], y = pb.quat[2], z = pb.quat[3];
+  float n = sqrtf(w * w + x * x + y * y + z * z);
+  w /= n; x /= n; y /= n; z /= n;
+  g.Rd[0] = 1.f - 2.f * (y * y + z * z); g.Rd[1] = 2.f * (x * y - w * z); g.Rd[2] = 2.f * (x * z + w * y);
+  g.Rd[3] = 2.f * (x * y + w * z); g.Rd[4] = 1.f - 2.f * (x * x + z * z); g.Rd[5] = 2.f * (y * z - w * x);
+  g.Rd[6] = 2.f * (x * z - w * y); g.Rd[7] = 2.f * (y * z + w * x); g.Rd[8] = 1.f - 2.f * (x * x + y * y);
+  g.pd[0] = pb.pd[0]; g.pd[1] = pb.pd[1]; g.pd[2] = pb.pd[2];
+  return g;
+}
+
+struct Sampler {
+  __amdgpu_buffer_rsrc_t rsrc;
+  float ox, oy, oz, inv_h, nxm1, nym1, nzm1;
+  int nxm2, nym2, nzm2, cx, cxy;   // cells along x, cells in an x-y layer
+};
+
+__device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
+  Sampler s;
+  s.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)sc.rec, (short)0, (int)sc.bytes, RSRC_DWORD3);
+  s.ox = sc.ox; s.oy = sc.oy; s.oz = sc.oz; s.inv_h = sc.inv_h;
+  s.nxm1 = (float)(sc.nx - 1); s.nym1 = (float)(sc.ny - 1); s.nzm1 = (float)(sc.nz - 1);
+  s.nxm2 = sc.nx - 2; s.nym2 = sc.ny - 2; s.nzm2 = sc.nz - 2;
+  s.cx = sc.nx - 1;
+  s.cxy = (sc.nx - 1) * (sc.ny - 1);
+  return s;
+}
+
+// Trilinear distance at p (clamped into the grid) and, with GRAD, its
+// spatial gradient (zero along clamped axes).  Cell along an axis is
+// min(floor(u), n-2) with u = (p - origin) / voxel.
+template <bool GRAD>
+__device__ __forceinline__ float sample(const Sampler& S, float px, float py, float pz, float& gx,
+                                        float& gy, float& gz) {
+  float ux = (px - S.ox) * S.inv_h;
+  float uy = (py - S.oy) * S.inv_h;
+  float uz = (pz - S.oz) * S.inv_h;
+  bool inx = ux >= 0.f && ux <= S.nxm1;
+  bool iny = uy >= 0.f && uy <= S.nym1;
+  bool inz = uz >= 0.f && uz <= S.nzm1;
+  ux = fminf(fmaxf(ux, 0.f), S.nxm1);
+  uy = fminf(fmaxf(uy, 0.f), S.nym1);
+  uz = fminf(fmaxf(uz, 0.f), S.nzm1);
+  int ix = min((int)ux, S.nxm2);
+  int iy = min((int)uy, S.nym2);
+  int iz = min((int)uz, S.nzm2);
+  float fx = ux - (float)ix, fy = uy - (float)iy, fz = uz - (float)iz;
+  int rec = ix + S.cx * iy + S.cxy * iz;
+  int off = rec * 32;
+  auto va = __builtin_amdgcn_raw_buffer_load_b128(S.rsrc, off, 0, 0);
+  auto vb = __builtin_amdgcn_raw_buffer_load_b128(S.rsrc, off + 16, 0, 0);
+  float4 a = *reinterpret_cast<float4*>(&va);   // z0: c000 c100 c010 c110
+  float4 b = *reinterpret_cast<float4*>(&vb);   // z1: c001 c101 c011 c111
+  float dx00 = a.y - a.x, dx10 = a.w - a.z, dx01 = b.y - b.x, dx11 = b.w - b.z;
+  float c00 = a.x + fx * dx00;
+  float c10 = a.z + fx * dx10;
+  float c01 = b.x + fx * dx01;
+  float c11 = b.z + fx * dx11;
+  float dy0 = c10 - c00, dy1 = c11 - c01;
+  float c0 = c00 + fy * dy0;
+  float c1 = c01 + fy * dy1;
+  float dz = c1 - c0;
+  float d = c0 + fz * dz;
+  if (GRAD) {
+    float e0 = dx00 + fy * (dx10 - dx00);
+    float e1 = dx01 + fy * (dx11 - dx01);
+    gx = inx ? (e0 + fz * (e1 - e0)) * S.inv_h : 0.f;
+    gy = iny ? (dy0 + fz * (dy1 - dy0)) * S.inv_h : 0.f;
+    gz = inz ? dz * S.inv_h : 0.f;
+  }
+  return d;
+}
+
+enum { EV_COST = 0, EV_GRAD = 1, EV_RESULT = 2 };
+
+struct EvalOut {
+  float cost;        // this lane's share of the seed objective (0 when inactive)
+  float g[NJ];       // gradient row (EV_GRAD; zero at t = 0 and inactive lanes)
+  float clr;         // min (distance - radius) at this waypoint (EV_RESULT)
+  float perr, rerr;  // goal errors at this lane's waypoint (EV_RESULT)
+};
+
+// Smoothness on the lane group: v_t = q_{t+1} - q_t (t <= T-2),
+// a_t = v_t - v_{t-1} (t < T), j_t = a_{t+1} - a_t (t < T) plus
+// j_{-1} = a_0 at t = 0 -- the first/second/third differences of the
+// sequence padded with two copies of q_0 and of q_{T-1}.  The gradient
+// applies the transposed stencils with the same shuffles.
+template <bool GRAD>
+__device__ __forceinline__ float smoothness(const ParamsDev& P, const float* q, int t, int T,
+                                            float* g) {
+  float c = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    float qn = __shfl_down(q[j], 1);
+    float v = (t <= T - 2) ? qn - q[j] : 0.f;
+    float vp = __shfl_up(v, 1);
+    float a = (t < T) ? v - (t >= 1 ? vp : 0.f) : 0.f;
+    float an = __shfl_down(a, 1);
+    float jk = (t < T) ? ((t + 1 < T ? an : 0.f) - a) : 0.f;
+    float jm = (t == 0) ? a : 0.f;   // j_{-1}
+    c += P.lv * (v * v) + P.la * (a * a) + P.lj * (jk * jk) + P.lj * (jm * jm);
+    if (GRAD) {
+      float jb = 2.f * P.lj * jk;
+      float jbp = __shfl_up(jb, 1);
+      float ab = (t < T) ? 2.f * P.la * a + ((t == 0) ? 2.f * P.lj * jm : jbp) - jb : 0.f;
+      float abn = __shfl_down(ab, 1);
+      float vb = (t <= T - 2) ? 2.f * P.lv * v + ab - abn : 0.f;
+      float vbp = __shfl_up(vb, 1);
+      g[j] += ((t >= 1) ? vbp : 0.f) - vb;
+    }
+  }
+  return c;
+}
+
+// One evaluation of the objective at this lane's configuration q.
+template <int MODE>
+__device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
+                                            const ParamsDev& P, const Sampler& S, const Goal& goal,
+                                            const float* q, int t, int T, bool active) {
+  constexpr bool GRAD = (MODE == EV_GRAD);
+  EvalOut o;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) o.g[j] = 0.f;
+  float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  float p[3] = {0.f, 0.f, 0.f};
+  float zs[NJ][3], os[NJ][3];
+  float phisum = 0.f, clr = FLT_MAX;
+#pragma unroll
+  for (int l = 0; l < NJ; ++l) {
+    const float* F = rb->F[l];
+    float A[9], pa[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        A[3 * r + c] = R[3 * r] * F[c] + R[3 * r + 1] * F[4 + c] + R[3 * r + 2] * F[8 + c];
+      pa[r] = R[3 * r] * F[3] + R[3 * r + 1] * F[7] + R[3 * r + 2] * F[11] + p[r];
+    }
+    float sn, cs;
+    sincosf(q[l], &sn, &cs);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      float a0 = A[3 * r], a1 = A[3 * r + 1];
+      R[3 * r] = cs * a0 + sn * a1;
+      R[3 * r + 1] = cs * a1 - sn * a0;
+      R[3 * r + 2] = A[3 * r + 2];
+      p[r] = pa[r];
+    }
+    if (GRAD) {
+      zs[l][0] = R[2]; zs[l][1] = R[5]; zs[l][2] = R[8];
+      os[l][0] = p[0]; os[l][1] = p[1]; os[l][2] = p[2];
+    }
+    float Fx = 0.f, Fy = 0.f, Fz = 0.f, Mx = 0.f, My = 0.f, Mz = 0.f;
+    const int s0 = rb->link_begin[l], s1 = rb->link_begin[l + 1];
+#pragma unroll 2
+    for (int s = s0; s < s1; ++s) {
+      float4 sp = rb->sph[s];
+      float cx = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
+      float cy = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
+      float cz = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
+      float gx, gy, gz;
+      float d = sample<GRAD>(S, cx, cy, cz, gx, gy, gz);
+      float D = d - sp.w;
+      float De = D - P.eps;
+      float phi = (D < 0.f) ? (0.5f * P.eps - D) : ((D < P.eps) ? De * De * P.half_inv_eps : 0.f);
+      phisum += phi;
+      if (MODE == EV_RESULT) clr = fminf(clr, D);
+      if (GRAD) {
+        float dphi = (D < 0.f) ? -1.f : ((D < P.eps) ? De * P.inv_eps : 0.f);
+        float w = P.wc * dphi;
+        float fx = w * gx, fy = w * gy, fz = w * gz;
+        Fx += fx; Fy += fy; Fz += fz;
+        Mx += cy * fz - cz * fy;
+        My += cz * fx - cx * fz;
+        Mz += cx * fy - cy * fx;
+      }
+    }
+    if (GRAD) {
+      // wrench of link l+1 on every joint i <= l: z_i . (M - o_i x F)
+#pragma unroll
+      for (int i = 0; i <= l; ++i) {
+        float tx = Mx - (os[i][1] * Fz - os[i][2] * Fy);
+        float ty = My - (os[i][2] * Fx - os[i][0] * Fz);
+        float tz = Mz - (os[i][0] * Fy - os[i][1] * Fx);
+        o.g[i] += zs[i][0] * tx + zs[i][1] * ty + zs[i][2] * tz;
+      }
+    }
+  }
+  // end effector and goal pose
+  const float* E = rb->Fee;
+  float Re[9], pe[3];
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+      Re[3 * r + c] = R[3 * r] * E[c] + R[3 * r + 1] * E[4 + c] + R[3 * r + 2] * E[8 + c];
+    pe[r] = R[3 * r] * E[3] + R[3 * r + 1] * E[7] + R[3 * r + 2] * E[11] + p[r];
+  }
+  float ex = pe[0] - goal.pd[0], ey = pe[1] - goal.pd[1], ez = pe[2] - goal.pd[2];
+  float tr = 0.f;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) tr += goal.Rd[k] * Re[k];
+  const bool last = (t == T - 1);
+  float goal_cost = P.wp * (ex * ex + ey * ey + ez * ez) + P.wr * (3.f - tr) * 0.25f;
+  if (GRAD && last) {
+    // force 2 w_p e at p_ee and torque -(w_r/4) w, w = vee(M - M^T), M = R_ee R_d^T
+    float M[9];
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = 0; b < 3; ++b)
+        M[3 * a + b] = Re[3 * a] * goal.Rd[3 * b] + Re[3 * a + 1] * goal.Rd[3 * b + 1] +
+                       Re[3 * a + 2] * goal.Rd[3 * b + 2];
+    float wx = M[5] - M[7], wy = M[6] - M[2], wz = M[1] - M[3];
+    float k2 = 2.f * P.wp, k4 = -0.25f * P.wr;
+    float fx = k2 * ex, fy = k2 * ey, fz = k2 * ez;
+#pragma unroll
+    for (int i = 0; i < NJ; ++i) {
+      float rx = pe[0] - os[i][0], ry = pe[1] - os[i][1], rz = pe[2] - os[i][2];
+      float tx = ry * fz - rz * fy + k4 * wx;
+      float ty = rz * fx - rx * fz + k4 * wy;
+      float tz = rx * fy - ry * fx + k4 * wz;
+      o.g[i] += zs[i][0] * tx + zs[i][1] * ty + zs[i][2] * tz;
+    }
+  }
+  if (MODE == EV_RESULT) {
+    o.perr = sqrtf(ex * ex + ey * ey + ez * ez);
+    // angle of R_d^T R_ee: cos = (tr - 1) / 2, sin = |vee(R_ee R_d^T)| / 2
+    float M5, M7, M6, M2, M1, M3;
+    M5 = Re[3] * goal.Rd[6] + Re[4] * goal.Rd[7] + Re[5] * goal.Rd[8];
+    M7 = Re[6] * goal.Rd[3] + Re[7] * goal.Rd[4] + Re[8] * goal.Rd[5];
+    M6 = Re[6] * goal.Rd[0] + Re[7] * goal.Rd[1] + Re[8] * goal.Rd[2];
+    M2 = Re[0] * goal.Rd[6] + Re[1] * goal.Rd[7] + Re[2] * goal.Rd[8];
+    M1 = Re[0] * goal.Rd[3] + Re[1] * goal.Rd[4] + Re[2] * goal.Rd[5];
+    M3 = Re[3] * goal.Rd[0] + Re[4] * goal.Rd[1] + Re[5] * goal.Rd[2];
+    float wx = M5 - M7, wy = M6 - M2, wz = M1 - M3;
+    o.rerr = atan2f(0.5f * sqrtf(wx * wx + wy * wy + wz * wz), 0.5f * (tr - 1.f));
+    o.clr = clr;
+  }
+  // joint limits
+  float lim = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    float hi = q[j] - rb->qhi[j], lo = rb->qlo[j] - q[j];
+    float hp = fmaxf(hi, 0.f), lp = fmaxf(lo, 0.f);
+    lim += hp * hp + lp * lp;
+    if (GRAD) o.g[j] += 2.f * P.wl * (hp - lp);
+  }
+  float sm = smoothness<GRAD>(P, q, t, T, o.g);
+  float c = P.wc * phisum + P.wl * lim + sm + (last ? goal_cost : 0.f);
+  o.cost = active ? c : 0.f;
+  if (GRAD) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) o.g[j] = (active && t > 0) ? o.g[j] : 0.f;
+  }
+  return o;
+}
+
+// ------------------------------------------------------------ optimiser ----
+
+struct TileCtx {
+  const RobotDev* rb;
+  ParamsDev P;
+  const ProbDev* pb;
+  Sampler S;
+  Goal goal;
+  float* st;
+  int lane, G, t, T, seed, gi;
+  bool valid, active;
+};
+
+__device__ __forceinline__ float* col(float* st, int base, int j, int lane) {
+  return st + base + j * WAVE + lane;
+}
+
+// L-BFGS direction (two-loop recursion over the ring in the tile state),
+// steepest-descent restart and infinity-norm cap.  cnt/head are this
+// lane's group's history count and ring head.
+__device__ __forceinline__ void direction(const TileCtx& c, const float* g, int& cnt, int head,
+                                          float* d) {
+  const int m = c.P.m;
+  float gmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) gmax = fmaxf(gmax, fabsf(g[j]));
+  gmax = grp_max(gmax, c.G);
+  float sc = c.P.delta0 / fmaxf(gmax, 1e-30f);
+  float steep[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) steep[j] = -g[j] * sc;
+
+  // wave-uniform loop bound: the longest history in the wave
+  int cmax = cnt;
+  for (int off = 1; off < WAVE; off <<= 1) cmax = max(cmax, __shfl_xor(cmax, off));
+  float q[NJ], a[DS_MAX_HISTORY];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) q[j] = g[j];
+#pragma unroll
+  for (int k = 0; k < DS_MAX_HISTORY; ++k) {
+    a[k] = 0.f;
+    if (k < cmax) {
+      int slot = (head - 1 - k + 2 * m) % m;
+      float s[NJ], y[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        s[j] = *col(c.st, ST_S + slot * NJ * WAVE, j, c.lane);
+        y[j] = *col(c.st, ST_Y + slot * NJ * WAVE, j, c.lane);
+      }
+      float rho = c.st[ST_RHO + slot * WAVE + c.lane];
+      float dt = grp_sum(dot7(s, q), c.G);
+      bool use = k < cnt;
+      float ak = rho * dt;
+      a[k] = use ? ak : 0.f;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) q[j] = use ? q[j] - ak * y[j] : q[j];
+    }
+  }
+  int newest = (head - 1 + m) % m;
+  float rho_n = c.st[ST_RHO + newest * WAVE + c.lane];
+  float yy_n = c.st[ST_YY + newest * WAVE + c.lane];
+  float gamma = 1.f / (rho_n * yy_n);   // s^T y / y^T y
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) q[j] *= gamma;
+#pragma unroll
+  for (int k = DS_MAX_HISTORY - 1; k >= 0; --k) {
+    if (k < cmax) {
+      int slot = (head - 1 - k + 2 * m) % m;
+      float s[NJ], y[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        s[j] = *col(c.st, ST_S + slot * NJ * WAVE, j, c.lane);
+        y[j] = *col(c.st, ST_Y + slot * NJ * WAVE, j, c.lane);
+      }
+      float rho = c.st[ST_RHO + slot * WAVE + c.lane];
+      float b = rho * grp_sum(dot7(y, q), c.G);
+      bool use = k < cnt;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) q[j] = use ? q[j] + s[j] * (a[k] - b) : q[j];
+    }
+  }
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) d[j] = (cnt > 0) ? -q[j] : steep[j];
+  float gtd = grp_sum(dot7(g, d), c.G);
+  if (!(gtd < 0.f)) {
+    cnt = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) d[j] = steep[j];
+  }
+  float dn = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) dn = fmaxf(dn, fabsf(d[j]));
+  dn = grp_max(dn, c.G);
+  if (dn > c.P.dmax) {
+    float f = c.P.dmax / dn;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) d[j] *= f;
+  }
+}
+
+__device__ __forceinline__ void trace_row(float* buf, const TileCtx& c, int k, const float* v) {
+  if (!buf || !c.valid || c.t >= c.T) return;
+  size_t base = (((size_t)k * c.pb->S + c.seed) * c.T + c.t) * NJ;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) buf[base + j] = v[j];
+}
+__device__ __forceinline__ void trace_scalar(float* buf, const TileCtx& c, int k, float v) {
+  if (!buf || !c.valid || c.t != 0) return;
+  buf[(size_t)k * c.pb->S + c.seed] = v;
+}
+
+// Final per-seed results and output trajectory.
+__device__ void finalize(const TileCtx& c, const float* x, float J) {
+  EvalOut r = evaluate<EV_RESULT>(c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.active);
+  float Jr = grp_sum(r.cost, c.G);
+  float clr = grp_min(c.active ? r.clr : FLT_MAX, c.G);
+  float perr = grp_sum((c.t == c.T - 1) ? r.perr : 0.f, c.G);
+  float rerr = grp_sum((c.t == c.T - 1) ? r.rerr : 0.f, c.G);
+  int inlim = 1;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) inlim &= (x[j] >= c.rb->qlo[j] && x[j] <= c.rb->qhi[j]) ? 1 : 0;
+  float okf = grp_min((c.active && !inlim) ? 0.f : 1.f, c.G);
+  // interior third differences
+  float jm = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    float q1 = __shfl_down(x[j], 1), q2 = __shfl_down(x[j], 2), q3 = __shfl_down(x[j], 3);
+    float v = q3 - 3.f * q2 + 3.f * q1 - x[j];
+    jm = fmaxf(jm, (c.t + 3 < c.T) ? fabsf(v) : 0.f);
+  }
+  jm = grp_max(jm, c.G);
+  if (c.valid && c.t < c.T) {
+    float* ft = c.pb->final_traj + ((size_t)c.seed * c.T + c.t) * NJ;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) ft[j] = x[j];
+    if (c.pb->out_traj) {
+      float* ot = c.pb->out_traj + ((size_t)c.seed * c.T + c.t) * NJ;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) ot[j] = x[j];
+    }
+  }
+  if (c.valid && c.t == 0) {
+    ds_seed_result sr;
+    sr.cost = Jr;
+    sr.clearance = clr;
+    sr.pos_err = perr;
+    sr.rot_err = rerr;
+    float dt3 = c.P.dt * c.P.dt * c.P.dt;
+    sr.max_jerk = jm / dt3;
+    sr.valid = isfinite(Jr) ? 1 : 0;
+    sr.collision_free = clr > 0.f ? 1 : 0;
+    sr.within_limits = okf > 0.5f ? 1 : 0;
+    sr.success = (sr.valid && sr.collision_free && sr.within_limits && perr < c.P.tol_pos &&
+                  rerr < c.P.tol_rot) ? 1 : 0;
+    sr.n_evals_cost = reinterpret_cast<const int*>(c.st)[ST_EVC + c.lane];
+    sr.n_evals_grad = reinterpret_cast<const int*>(c.st)[ST_EVG + c.lane];
+    sr.pad = 0;
+    c.pb->seed_res[c.seed] = sr;
+  }
+  (void)J;
+}
+
+// Run up to max_iters iterations of one tile (state persists in the arena).
+__device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
+                         const ProbDev* __restrict__ probs, const TileDev& td, int max_iters) {
+  TileCtx c;
+  c.rb = rb;
+  c.P = *pp;
+  c.pb = probs + td.prob;
+  c.S = make_sampler(c.pb->sc);
+  c.goal = make_goal(*c.pb);
+  c.st = td.state;
+  c.lane = threadIdx.x & (WAVE - 1);
+  c.G = td.G;
+  c.t = c.lane & (c.G - 1);
+  c.gi = c.lane / c.G;
+  c.T = c.pb->T;
+  c.seed = td.seed0 + c.gi;
+  c.valid = c.gi < td.nseed;
+  c.active = c.valid && c.t < c.T;
+  const int n_iters = c.pb->n_iters;
+  int* sti = reinterpret_cast<int*>(c.st);
+
+  float x[NJ], g[NJ], J;
+  int cnt, head, iter, evc, evg;
+  iter = sti[ST_ITER + c.lane];
+  if (iter == 0) {
+    if (c.active) {
+      const float* sp = c.pb->seeds + ((size_t)c.seed * c.T + c.t) * NJ;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) x[j] = (c.t == 0) ? c.pb->qs[j] : sp[j];
+    } else {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) x[j] = 0.f;
+    }
+    EvalOut e = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, x, c.t, c.T, c.active);
+    J = grp_sum(e.cost, c.G);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) g[j] = e.g[j];
+    cnt = 0;
+    head = 0;
+    evc = 0;
+    evg = 1;
+  } else {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      x[j] = *col(c.st, ST_X, j, c.lane);
+      g[j] = *col(c.st, ST_G, j, c.lane);
+    }
+    J = c.st[ST_J + c.lane];
+    cnt = sti[ST_CNT + c.lane];
+    head = sti[ST_HEAD + c.lane];
+    evc = sti[ST_EVC + c.lane];
+    evg = sti[ST_EVG + c.lane];
+  }
+  const int n_run = min(max_iters, n_iters - iter);
+  const ProbDev& pb = *c.pb;
+  for (int k = 0; k < n_run; ++k, ++iter) {
+    trace_row(pb.tr_x, c, iter, x);
+    trace_row(pb.tr_g, c, iter, g);
+    trace_scalar(pb.tr_J, c, iter, J);
+    float d[NJ];
+    direction(c, g, cnt, head, d);
+    trace_row(pb.tr_d, c, iter, d);
+    const float gtd = grp_sum(dot7(g, d), c.G);
+    // candidate alpha = 1 with its gradient
+    float xt[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) xt[j] = x[j] + d[j];
+    EvalOut e = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, xt, c.t, c.T, c.active);
+    ++evg;
+    float Jt = grp_sum(e.cost, c.G);
+    float gt[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) gt[j] = e.g[j];
+    int chosen = (Jt <= J + c.P.c1 * gtd) ? 0 : -1;
+    float Jmin = Jt;
+    int kmin = 0;
+    for (int kk = 1; kk < c.P.nls; ++kk) {
+      bool need = chosen < 0;
+      if (!__any(need)) break;
+      float al = ldexpf(1.f, -kk);
+      float xk[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) xk[j] = x[j] + al * d[j];
+      EvalOut ek = evaluate<EV_COST>(rb, c.P, c.S, c.goal, xk, c.t, c.T, c.active);
+      ++evc;
+      float Jk = grp_sum(ek.cost, c.G);
+      if (need && Jk <= J + c.P.c1 * al * gtd) chosen = kk;
+      if (need && Jk < Jmin) { Jmin = Jk; kmin = kk; }
+    }
+    if (chosen < 0 && Jmin < J) chosen = kmin;
+    const float alpha = chosen >= 0 ? ldexpf(1.f, -chosen) : 0.f;
+    if (__any(chosen > 0)) {
+      float al = chosen > 0 ? alpha : 1.f;
+      float xa[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) xa[j] = x[j] + al * d[j];
+      EvalOut ea = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, xa, c.t, c.T, c.active);
+      ++evg;
+      float Ja = grp_sum(ea.cost, c.G);
+      if (chosen > 0) {
+        Jt = Ja;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) { gt[j] = ea.g[j]; xt[j] = xa[j]; }
+      }
+    }
+    trace_scalar(pb.tr_a, c, iter, alpha);
+    const bool accept = chosen >= 0;
+    float s[NJ], y[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      s[j] = accept ? xt[j] - x[j] : 0.f;
+      y[j] = accept ? gt[j] - g[j] : 0.f;
+    }
+    float sy = grp_sum(dot7(s, y), c.G);
+    float ss = grp_sum(dot7(s, s), c.G);
+    float yy = grp_sum(dot7(y, y), c.G);
+    if (accept) {
+      if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy)) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          *col(c.st, ST_S + head * NJ * WAVE, j, c.lane) = s[j];
+          *col(c.st, ST_Y + head * NJ * WAVE, j, c.lane) = y[j];
+        }
+        c.st[ST_RHO + head * WAVE + c.lane] = 1.f / sy;
+        c.st[ST_YY + head * WAVE + c.lane] = yy;
+        head = (head + 1) % c.P.m;
+        cnt = min(cnt + 1, c.P.m);
+      }
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) { x[j] = xt[j]; g[j] = gt[j]; }
+      J = Jt;
+    } else {
+      cnt = 0;
+    }
+  }
+  // persist the state
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) {
+    *col(c.st, ST_X, j, c.lane) = x[j];
+    *col(c.st, ST_G, j, c.lane) = g[j];
+  }
+  c.st[ST_J + c.lane] = J;
+  sti[ST_CNT + c.lane] = cnt;
+  sti[ST_HEAD + c.lane] = head;
+  sti[ST_ITER + c.lane] = iter;
+  sti[ST_EVC + c.lane] = evc;
+  sti[ST_EVG + c.lane] = evg;
+  if (iter == n_iters && n_run >= 0) {
+    if (n_run > 0 || max_iters >= 0) {
+      trace_row(pb.tr_x, c, iter, x);
+      trace_row(pb.tr_g, c, iter, g);
+      trace_scalar(pb.tr_J, c, iter, J);
+    }
+    finalize(c, x, J);
+  }
+}
+
+// Persistent optimiser: every wavefront takes tiles from an atomic counter
+// until the table is exhausted (tile_list, if given, indirects the table;
+// n_tiles_dev, if given, overrides n_tiles).
+__global__ void __launch_bounds__(BLOCK)
+k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
+           const ProbDev* __restrict__ probs, const TileDev* __restrict__ tiles,
+           const int* __restrict__ tile_list, const int* __restrict__ n_tiles_dev, int n_tiles,
+           int* counter, int max_iters) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int nt = n_tiles_dev ? *n_tiles_dev : n_tiles;
+  for (;;) {
+    int mine = 0;
+    if (lane == 0) mine = atomicAdd(counter, 1);
+    mine = __builtin_amdgcn_readfirstlane(__shfl(mine, 0));
+    if (mine >= nt) break;
+    const int ti = tile_list ? tile_list[mine] : mine;
+    TileDev td = tiles[ti];
+    run_tile(rb, pp, probs, td, max_iters);
+  }
+}
+
+// Best seed per problem: lowest cost among successful seeds (ties: lowest
+// index), else lowest cost among valid seeds.
+__global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs) {
+  const ProbDev& pb = probs[blockIdx.x];
+  __shared__ int s_any;
+  __shared__ unsigned long long s_key[2];
+  __shared__ int s_valid;
+  if (threadIdx.x == 0) { s_any = 0; s_key[0] = ~0ull; s_key[1] = ~0ull; s_valid = 0; }
+  __syncthreads();
+  for (int s = threadIdx.x; s < pb.S; s += blockDim.x) {
+    const ds_seed_result& r = pb.seed_res[s];
+    if (r.valid) {
+      atomicAdd(&s_valid, 1);
+      // order-preserving key of a finite float cost, then the index
+      unsigned u = __float_as_uint(r.cost);
+      u = (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+      unsigned long long key = ((unsigned long long)u << 32) | (unsigned)s;
+      atomicMin(&s_key[0], key);
+      if (r.success) { atomicMin(&s_key[1], key); s_any = 1; }
+    }
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    ds_result out;
+    unsigned long long key = s_any ? s_key[1] : s_key[0];
+    int best = (key == ~0ull) ? -1 : (int)(key & 0xffffffffu);
+    out.best_seed = best;
+    out.n_valid_seeds = s_valid;
+    out.n_iters = pb.n_iters;
+    if (best >= 0) {
+      const ds_seed_result& r = pb.seed_res[best];
+      out.success = r.success;
+      out.collision_free = r.collision_free;
+      out.pos_err_m = r.pos_err;
+      out.rot_err_rad = r.rot_err;
+      out.cost = r.cost;
+      out.min_clearance_m = r.clearance;
+      out.max_jerk = r.max_jerk;
+    } else {
+      out.success = 0;
+      out.collision_free = 0;
+      out.pos_err_m = out.rot_err_rad = out.cost = out.min_clearance_m = out.max_jerk = NAN;
+    }
+    *pb.result = out;
+  }
+}
+
+// Objective (and gradient) of arbitrary trajectories: one wavefront per
+// seed group of G lanes (G = smallest of 16/32/64 holding T).
+__global__ void __launch_bounds__(BLOCK)
+k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
+       const ProbDev* __restrict__ pb, const float* __restrict__ X, int S, int T, int G,
+       const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
+       int with_grad) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int wave = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+  const int per = WAVE / G;
+  const int gi = lane / G, t = lane & (G - 1);
+  const int seed = wave * per + gi;
+  if (wave * per >= S) return;   // whole wavefront past the end
+  const bool active = seed < S && t < T;
+  ParamsDev P = *pp;
+  Sampler Sm = make_sampler(pb->sc);
+  Goal goal = make_goal(*pb);
+  float x[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) x[j] = active ? X[((size_t)seed * T + t) * NJ + j] : 0.f;
+  float J;
+  if (with_grad) {
+    EvalOut e = evaluate<EV_GRAD>(rb, P, Sm, goal, x, t, T, active);
+    J = grp_sum(e.cost, G);
+    float w = (dJ && seed < S) ? dJ[seed] : 1.f;
+    if (active) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) dX[((size_t)seed * T + t) * NJ + j] = w * e.g[j];
+    }
+  } else {
+    EvalOut e = evaluate<EV_COST>(rb, P, Sm, goal, x, t, T, active);
+    J = grp_sum(e.cost, G);
+  }
+  if (J_out && seed < S && t == 0) J_out[seed] = J;
+}
+
+// Sphere centres (parity dump), one thread per seed-waypoint.
+__global__ void k_spheres(const RobotDev* __restrict__ rb, const float* __restrict__ X, int n,
+                          float* __restrict__ out) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float q[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) q[j] = X[(size_t)i * NJ + j];
+  float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  float p[3] = {0.f, 0.f, 0.f};
+  const int ns = rb->ns;
+  for (int l = 0; l < NJ; ++l) {
+    const float* F = rb->F[l];
+    float A[9], pa[3];
+    for (int r = 0; r < 3; ++r) {
+      for (int c = 0; c < 3; ++c)
+        A[3 * r + c] = R[3 * r] * F[c] + R[3 * r + 1] * F[4 + c] + R[3 * r + 2] * F[8 + c];
+      pa[r] = R[3 * r] * F[3] + R[3 * r + 1] * F[7] + R[3 * r + 2] * F[11] + p[r];
+    }
+    float sn, cs;
+    sincosf(q[l], &sn, &cs);
+    for (int r = 0; r < 3; ++r) {
+      float a0 = A[3 * r], a1 = A[3 * r + 1];
+      R[3 * r] = cs * a0 + sn * a1;
+      R[3 * r + 1] = cs * a1 - sn * a0;
+      R[3 * r + 2] = A[3 * r + 2];
+      p[r] = pa[r];
+    }
+    for (int s = rb->link_begin[l]; s < rb->link_begin[l + 1]; ++s) {
+      float4 sp = rb->sph[s];
+      float* o = out + ((size_t)i * ns + rb->perm[s]) * 3;
+      o[0] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
+      o[1] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
+      o[2] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
+    }
+  }
+}
+
+// x-fastest node values -> 8-corner cell records.
+__global__ void k_esdf_pack(const float* __restrict__ v, int nx, int ny, int nz,
+                            float4* __restrict__ rec) {
+  const long long cx = nx - 1, cy = ny - 1, cz = nz - 1;
+  const long long n = cx * cy * cz;
+  for (long long r = blockIdx.x * (long long)blockDim.x + threadIdx.x; r < n;
+       r += (long long)gridDim.x * blockDim.x) {
+    long long i = r % cx, j = (r / cx) % cy, k = r / (cx * cy);
+    auto at = [&](long long a, long long b, long long c) { return v[a + nx * (b + (long long)ny * c)]; };
+    rec[2 * r] = make_float4(at(i, j, k), at(i + 1, j, k), at(i, j + 1, k), at(i + 1, j + 1, k));
+    rec[2 * r + 1] = make_float4(at(i, j, k + 1), at(i + 1, j, k + 1), at(i, j + 1, k + 1),
+                                 at(i + 1, j + 1, k + 1));
+  }
+}
+
+__global__ void k_zero_i32(int* p, int n) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = 0;
+}
+
+}  // namespace
+
+hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* rec,
+                            hipStream_t s) {
+  long long n = (long long)(nx - 1) * (ny - 1) * (nz - 1);
+  int blocks = (int)std::min<long long>((n + 255) / 256, 65536);
+  hipLaunchKernelGGL(k_esdf_pack, dim3(blocks), dim3(256), 0, s, vals, nx, ny, nz, rec);
+  return hipGetLastError();
+}
+
+hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
+                           const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
+                           int max_iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(BLOCK), 0, s, rb, pp, probs, tiles,
+                     (const int*)nullptr, (const int*)nullptr, n_tiles, counter, max_iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
+                             const TileDev* tiles, const int* tile_list, int* counter,
+                             int max_tiles, int grid_blocks, int max_iters, hipStream_t s) {
+  // tile_list[0] holds the number of listed tiles, the indices follow
+  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(BLOCK), 0, s, rb, pp, probs, tiles,
+                     tile_list + 1, tile_list, max_tiles, counter, max_iters);
+  return hipGetLastError();
+}
+
+hipError_t launch_best(const ProbDev* probs, int n_probs, hipStream_t s) {
+  hipLaunchKernelGGL(k_best, dim3(n_probs), dim3(256), 0, s, probs);
+  return hipGetLastError();
+}
+
+hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
+                       const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
+                       int with_grad, hipStream_t s) {
+  int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
+  int per = WAVE / G;
+  int waves = (S + per - 1) / per;
+  int blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, dJ,
+                     J_out, dX, with_grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
+                          hipStream_t s) {
+  int n = S * T;
+  hipLaunchKernelGGL(k_spheres, dim3((n + 255) / 256), dim3(256), 0, s, rb, X, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_zero_i32(int* p, int n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_i32, dim3((n + 255) / 256), dim3(256), 0, s, p, n);
+  return hipGetLastError();
+}
+
+}  // namespace dsk

@@ -1,0 +1,213 @@
+"""GPU parity: the gfx950 library against the FP64 oracle on the same
+seeded inputs, through the C ABI.
+
+Tolerances (spec contract of this path): sphere centres within
+1e-5 m; costs within 1e-4 relative; gradients within 1e-4 of the gradient
+scale (the larger of |g|_inf and the largest per-element sum of absolute
+contributions -- the float32 sum cannot do better than that scale) plus the
+oracle's bound for samples within 1e-4 voxel of a trilinear cell face,
+where a float32 caller may legitimately take the neighbouring cell;
+per-seed flags exactly, except seeds whose deciding margin is below the
+float32 resolution (reported as ambiguous)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_2410_16727_amd import dsopt  # noqa: E402
+from workloads import configs, gen, params  # noqa: E402
+
+P = params.DEFAULT
+COST_RTOL = 1e-4
+GRAD_RTOL = 1e-4
+AMB_TOL = 1e-4
+
+
+def say(*a):
+    print(*a, flush=True)
+
+
+class Setup:
+    def __init__(self, key, iters=None):
+        self.key = key
+        self.robot = configs.robot(key)
+        self.scene = configs.scenes(key, only={0})[0]
+        self.prob = configs.problems(key)[0]
+        self.iters = iters if iters is not None else configs.WORKLOADS[key].iters
+        self.plan = dsopt.Plan(self.robot, P, self.iters, 512 << 20)
+        self.plan.upload_scene(0, self.scene.grid, self.scene.voxel, self.scene.origin)
+        self.O = oracle.Oracle(self.robot, self.scene, params.as_list(), threads=8)
+
+
+_setups = {}
+
+
+def setup(key, iters=None):
+    k = (key, iters)
+    if k not in _setups:
+        _setups[k] = Setup(key, iters)
+    return _setups[k]
+
+
+def random_trajs(seed, S, T, q_start, spread=1.0):
+    rng = np.random.default_rng(seed)
+    return gen.random_trajectories(rng, S, T, q_start, scale=spread)
+
+
+def check_cost_grad(su, X):
+    say(f"cost/grad parity {su.key} S={X.shape[0]} T={X.shape[1]}")
+    Xd = torch.from_numpy(X).cuda()
+    J, G = su.plan.cost_grad(0, su.prob.q_start, su.prob.goal, Xd)
+    J2 = su.plan.cost(0, su.prob.q_start, su.prob.goal, Xd)
+    torch.cuda.synchronize()
+    J, G, J2 = J.cpu().numpy(), G.cpu().numpy(), J2.cpu().numpy()
+    ref = su.O.cost(su.prob.q_start, su.prob.goal, X.astype(np.float64), grad=True, absg=True)
+    rel = np.abs(J - ref["J"]) / np.abs(ref["J"])
+    assert rel.max() < COST_RTOL, rel.max()
+    assert np.abs(J2 - ref["J"]).max() / np.abs(ref["J"]).min() < COST_RTOL
+    for s in range(X.shape[0]):
+        amb, _ = su.O.ambiguity(X[s].astype(np.float64), AMB_TOL)
+        scale = max(np.abs(ref["G"][s]).max(), np.abs(ref["A"][s]).max())
+        err = np.abs(G[s] - ref["G"][s]) - amb
+        assert err.max() <= GRAD_RTOL * scale, (s, err.max() / scale)
+    assert np.all(G[:, 0, :] == 0)
+    return rel.max()
+
+
+@pytest.mark.parametrize("key", ["A", "B", "C"])
+def test_sphere_centres(key):
+    su = setup(key, 1)
+    X = random_trajs(1, 8, 16, su.prob.q_start)
+    say(f"sphere centres {key}")
+    c = su.plan.sphere_centres(torch.from_numpy(X).cuda()).cpu().numpy()
+    for s in range(X.shape[0]):
+        ref = su.O.spheres(X[s].astype(np.float64))
+        assert np.abs(c[s] - ref).max() < 1e-5
+
+
+@pytest.mark.parametrize("key", ["A", "B"])
+def test_cost_grad_random_trajectories(key):
+    su = setup(key, 1)
+    X = random_trajs(2, 16, 32, su.prob.q_start)
+    check_cost_grad(su, X)
+
+
+@pytest.mark.parametrize("T", [4, 5, 15, 16, 17, 31, 32, 33, 63, 64])
+def test_cost_grad_horizons(T):
+    su = setup("B", 1)
+    X = random_trajs(100 + T, 5, T, su.prob.q_start)
+    check_cost_grad(su, X)
+
+
+def test_cost_grad_full_size_differentiation_workload():
+    """256 seeds x 64 waypoints, 60 spheres, 200^3 grid (the full
+    differentiation workload), seeds plus trajectories driven into the
+    shelves."""
+    su = setup("C", 1)
+    X = configs.seeds_for("C", 0, su.prob)
+    X[128:] = random_trajs(3, 128, 64, su.prob.q_start)
+    check_cost_grad(su, X)
+
+
+def run_traced(su, S=None, T=None, tag=7):
+    seeds = configs.seeds_for(su.key, 0, su.prob, S=S, T=T)
+    say(f"traced optimisation {su.key} S={seeds.shape[0]} T={seeds.shape[1]} iters={su.iters}")
+    sd = torch.from_numpy(seeds).cuda()
+    tr = su.plan.optimize_traced({"scene": 0, "q_start": su.prob.q_start, "goal": su.prob.goal,
+                                  "seeds": sd, "tag": tag})
+    torch.cuda.synchronize()
+    tr = {k: v.double().cpu().numpy() for k, v in tr.items()}
+    return seeds, tr
+
+
+def lockstep_check(su, tr, S):
+    worst = np.zeros(4)
+    ties = 0
+    for s in range(S):
+        rep = su.O.lockstep(su.prob.q_start, su.prob.goal, tr["x"][:, s], tr["g"][:, s],
+                            tr["J"][:, s], tr["d"][:, s], tr["alpha"][:, s], AMB_TOL)
+        near_tie = rep[:, 5] < 1e-4
+        ties += int(near_tie.sum())
+        worst[0] = max(worst[0], rep[:, 0].max())
+        worst[1] = max(worst[1], rep[:, 1].max())
+        assert rep[:, 0].max() < COST_RTOL, (s, rep[:, 0].max())
+        assert rep[:, 1].max() < GRAD_RTOL, (s, rep[:, 1].max())
+        # the direction is recomputed from the same history in FP64
+        assert rep[:, 3].max() < 1e-3, (s, rep[:, 3].max())
+        # the accepted step: identical unless the decision is a near tie
+        agree = (rep[:, 4] == tr["alpha"][:, s]) | near_tie
+        assert agree.all(), (s, np.nonzero(~agree))
+        # x_{k+1} = x_k + alpha_k d_k (float32 rounding only)
+        assert rep[:, 6].max() < 1e-5
+    say(f"lockstep worst cost {worst[0]:.2e} grad {worst[1]:.2e} near-ties {ties}")
+    return ties
+
+
+@pytest.mark.parametrize("key", ["A", "B"])
+def test_lockstep_iterations(key):
+    su = setup(key)
+    seeds, tr = run_traced(su)
+    lockstep_check(su, tr, seeds.shape[0])
+    su.plan.release(7)
+
+
+@pytest.mark.parametrize("key", ["A", "B"])
+def test_flags_match_oracle_on_final_trajectories(key):
+    su = setup(key)
+    seeds, tr = run_traced(su, tag=8)
+    S, T = seeds.shape[0], seeds.shape[1]
+    res = su.plan.seed_results(8, S)
+    traj, best = su.plan.get_best(8, T)
+    Xf = tr["x"][-1]
+    ref = su.O.results(su.prob.q_start, su.prob.goal, Xf)
+    amb = np.abs(ref["clearance"]) < 1e-5
+    for f in ["collision_free", "within_limits", "success", "valid"]:
+        ok = (res[f] == ref[f].astype(int)) | amb
+        assert ok.all(), (f, res[f], ref[f])
+    assert np.abs(res["cost"] - ref["J"]).max() / np.abs(ref["J"]).max() < COST_RTOL
+    assert np.abs(res["clearance"] - ref["clearance"]).max() < 1e-4
+    assert np.abs(res["pos_err"] - ref["pos_err"]).max() < 1e-5
+    assert np.abs(res["rot_err"] - ref["rot_err"]).max() < 1e-3
+    # best seed: the oracle's rule on the GPU's per-seed costs
+    if not amb.any():
+        assert best["best_seed"] == ref["best"] or \
+            abs(ref["J"][best["best_seed"]] - ref["J"][ref["best"]]) < 1e-4 * ref["J"][ref["best"]]
+    assert np.array_equal(traj, tr["x"][-1][best["best_seed"]].astype(np.float32))
+    su.plan.release(8)
+
+
+def test_invalid_inputs_are_rejected():
+    su = setup("A", 1)
+    seeds = torch.zeros((2, 8, 7), device="cuda")
+    good = {"scene": 0, "q_start": su.prob.q_start, "goal": su.prob.goal, "seeds": seeds,
+            "tag": 99}
+    for bad, code in [({"scene": 5}, dsopt.DS_ERR_NOT_FOUND),
+                      ({"seeds": torch.zeros((2, 3, 7), device="cuda")}, dsopt.DS_ERR_INVALID),
+                      ({"seeds": torch.zeros((2, 65, 7), device="cuda")}, dsopt.DS_ERR_INVALID),
+                      ({"seeds": torch.zeros((0, 8, 7), device="cuda")}, dsopt.DS_ERR_INVALID),
+                      ({"goal": np.array([0, 0, 0, 0, 0, 0, 0], dtype=np.float32)},
+                       dsopt.DS_ERR_INVALID)]:
+        with pytest.raises(dsopt.DsError) as e:
+            su.plan.optimize([dict(good, **bad)])
+        assert e.value.code == code
+    with pytest.raises(dsopt.DsError):
+        su.plan.upload_scene(3, np.zeros((1, 4, 4), dtype=np.float32), 0.1, (0, 0, 0))
+
+
+def test_determinism_bitwise():
+    su = setup("B")
+    seeds = torch.from_numpy(configs.seeds_for("B", 0, su.prob)).cuda()
+    outs = []
+    for tag in (21, 22):
+        out = torch.zeros_like(seeds)
+        su.plan.optimize([{"scene": 0, "q_start": su.prob.q_start, "goal": su.prob.goal,
+                           "seeds": seeds, "tag": tag, "out": out}])
+        torch.cuda.synchronize()
+        outs.append(out.cpu().numpy())
+        su.plan.release(tag)
+    assert np.array_equal(outs[0], outs[1])
