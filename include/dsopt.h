@@ -214,6 +214,13 @@ int ds_cost_grad(ds_plan* plan, const ds_problem* prob, const float* X, int S, i
  * [S][T][n_spheres][3]), in the robot's sphere order (parity checks). */
 int ds_sphere_centres(ds_plan* plan, const float* X, int S, int T, float* out, void* stream);
 
+/* Kernel timing: when enabled, every optimiser-kernel launch of the plan is
+ * bracketed by HIP events on its stream; ds_kernel_timing_read waits for
+ * the recorded launches and returns their summed duration (milliseconds)
+ * and count since the last read.  For measurement only. */
+int ds_kernel_timing(ds_plan* plan, int enable);
+int ds_kernel_timing_read(ds_plan* plan, double* total_ms, int64_t* launches);
+
 /* ---- serving: continuous batching of planning requests -------------------
  * Requests are admitted into device slots while memory and slots allow;
  * every step runs params.block_iters iterations of every admitted request

@@ -150,6 +150,9 @@ struct ds_plan {
   size_t staging_cap = 0, staging_pos = 0;
   std::vector<hipEvent_t> staging_events;
   int cu_count = 0, blocks_per_cu = 1;
+  // optional kernel timing: (start, stop) event pairs not yet read
+  bool timing = false;
+  std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
   // serving
   struct Serve* serve = nullptr;
 };
@@ -299,6 +302,27 @@ void free_problem(ds_plan* p, ProblemRec& rec) {
   }
 }
 
+}  // namespace
+
+// Launch `fn` on stream s, bracketed by timing events when enabled.
+template <class Fn>
+int timed_launch(ds_plan* p, hipStream_t s, Fn fn) {
+  hipEvent_t a = nullptr, b = nullptr;
+  if (p->timing) {
+    HIP_TRY(hipEventCreate(&a));
+    HIP_TRY(hipEventCreate(&b));
+    HIP_TRY(hipEventRecord(a, s));
+  }
+  HIP_TRY(fn());
+  if (p->timing) {
+    HIP_TRY(hipEventRecord(b, s));
+    p->timed.emplace_back(a, b);
+  }
+  return DS_OK;
+}
+
+namespace {
+
 int tiles_for(int S, int T) {
   int per = WAVE / group_size(T);
   return (S + per - 1) / per;
@@ -384,8 +408,11 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   int waves_needed = total_tiles;
   int blocks = (waves_needed + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   blocks = std::max(1, std::min(blocks, p->cu_count * p->blocks_per_cu));
-  HIP_TRY(launch_optimize(p->robot_dev, p->params_dev, pd_dev, td_dev, total_tiles, counter,
-                          blocks, p->params.n_iters, s));
+  if (int rc = timed_launch(p, s, [&]() {
+        return launch_optimize(p->robot_dev, p->params_dev, pd_dev, td_dev, total_tiles, counter,
+                               blocks, p->params.n_iters, s);
+      }))
+    return rc;
   HIP_TRY(launch_best(pd_dev, n, s));
   launch->done = get_event(p);
   if (!launch->done) return fail(DS_ERR_HIP, "event creation failed");
@@ -631,6 +658,29 @@ int ds_cost(ds_plan* p, const ds_problem* prob, const float* X, int S, int T, fl
 int ds_cost_grad(ds_plan* p, const ds_problem* prob, const float* X, int S, int T,
                  const float* dJ, float* J_out, float* dX, void* stream) {
   return cost_common(p, prob, X, S, T, dJ, J_out, dX, 1, stream);
+}
+
+int ds_kernel_timing(ds_plan* p, int enable) {
+  if (!p) return fail(DS_ERR_INVALID, "NULL plan");
+  p->timing = enable != 0;
+  return DS_OK;
+}
+
+int ds_kernel_timing_read(ds_plan* p, double* total_ms, int64_t* launches) {
+  if (!p || !total_ms || !launches) return fail(DS_ERR_INVALID, "NULL argument");
+  double tot = 0;
+  for (auto& ab : p->timed) {
+    HIP_TRY(hipEventSynchronize(ab.second));
+    float ms = 0;
+    HIP_TRY(hipEventElapsedTime(&ms, ab.first, ab.second));
+    tot += ms;
+    hipEventDestroy(ab.first);
+    hipEventDestroy(ab.second);
+  }
+  *total_ms = tot;
+  *launches = (int64_t)p->timed.size();
+  p->timed.clear();
+  return DS_OK;
 }
 
 int ds_sphere_centres(ds_plan* p, const float* X, int S, int T, float* out, void* stream) {

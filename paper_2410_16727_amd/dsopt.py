@@ -30,7 +30,7 @@ EXPORTED = [
     "ds_esdf_release", "ds_optimize_seeds", "ds_optimize_traced", "ds_get_best",
     "ds_get_seed_results", "ds_problem_release", "ds_cost", "ds_cost_grad",
     "ds_sphere_centres", "ds_serve_start", "ds_serve_submit", "ds_serve_step", "ds_serve_poll",
-    "ds_serve_stats", "ds_serve_stop",
+    "ds_serve_stats", "ds_serve_stop", "ds_kernel_timing", "ds_kernel_timing_read",
 ]
 
 
@@ -117,6 +117,8 @@ def load():
     L.ds_cost_grad.argtypes = [vp, C.POINTER(Problem), f32p, C.c_int, C.c_int, f32p, f32p, f32p,
                                vp]
     L.ds_sphere_centres.argtypes = [vp, f32p, C.c_int, C.c_int, f32p, vp]
+    L.ds_kernel_timing.argtypes = [vp, C.c_int]
+    L.ds_kernel_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.ds_serve_start.argtypes = [vp, C.c_int, C.c_int, vp]
     L.ds_serve_submit.argtypes = [vp, C.POINTER(Problem), C.POINTER(C.c_uint64)]
     L.ds_serve_step.argtypes = [vp]
@@ -319,6 +321,16 @@ class Plan:
         out = torch.empty((S, T, self.n_spheres, 3), dtype=torch.float32, device=X.device)
         check(self.lib.ds_sphere_centres(self.h, _ptr(X), S, T, _ptr(out), _stream(stream)))
         return out
+
+    # -- measurement ------------------------------------------------------------------
+    def kernel_timing(self, enable=True):
+        check(self.lib.ds_kernel_timing(self.h, 1 if enable else 0))
+
+    def kernel_timing_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        check(self.lib.ds_kernel_timing_read(self.h, C.byref(ms), C.byref(n)))
+        return ms.value, n.value
 
     # -- serving ---------------------------------------------------------------------
     def serve_start(self, max_slots, queue_cap, stream=None):
