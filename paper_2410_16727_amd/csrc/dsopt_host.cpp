@@ -14,12 +14,9 @@
 #include <string>
 #include <vector>
 
-#include "dsopt.h"
-#include "dsopt_internal.h"
+#include "dsopt_plan.h"
 
-using namespace dsk;
-
-namespace {
+namespace dsh {
 
 thread_local std::string g_err;
 
@@ -32,132 +29,6 @@ int fail(int code, const char* fmt, ...) {
   g_err = buf;
   return code;
 }
-
-#define HIP_TRY(expr)                                                              \
-  do {                                                                             \
-    hipError_t e_ = (expr);                                                        \
-    if (e_ != hipSuccess)                                                          \
-      return fail(DS_ERR_HIP, "%s failed: %s", #expr, hipGetErrorString(e_));      \
-  } while (0)
-
-// ------------------------------------------------------------------ arena --
-// First-fit sub-allocator over the caller's device buffer (bookkeeping on
-// the host only; 256-byte alignment; neighbours coalesce on free).
-class Arena {
- public:
-  void init(uint8_t* base, size_t size) {
-    base_ = base;
-    size_ = size;
-    free_.clear();
-    free_[0] = size;
-    used_ = 0;
-  }
-  // returns offset or SIZE_MAX
-  size_t alloc(size_t bytes) {
-    bytes = (bytes + 255) / 256 * 256;
-    if (bytes == 0) bytes = 256;
-    for (auto it = free_.begin(); it != free_.end(); ++it) {
-      if (it->second >= bytes) {
-        size_t off = it->first, len = it->second;
-        free_.erase(it);
-        if (len > bytes) free_[off + bytes] = len - bytes;
-        live_[off] = bytes;
-        used_ += bytes;
-        return off;
-      }
-    }
-    return SIZE_MAX;
-  }
-  void release(size_t off) {
-    auto it = live_.find(off);
-    if (it == live_.end()) return;
-    size_t len = it->second;
-    live_.erase(it);
-    used_ -= len;
-    auto nx = free_.lower_bound(off);
-    if (nx != free_.end() && off + len == nx->first) {
-      len += nx->second;
-      free_.erase(nx);
-    }
-    auto pv = free_.lower_bound(off);
-    if (pv != free_.begin()) {
-      --pv;
-      if (pv->first + pv->second == off) {
-        pv->second += len;
-        return;
-      }
-    }
-    free_[off] = len;
-  }
-  size_t largest_free() const {
-    size_t m = 0;
-    for (auto& kv : free_) m = std::max(m, kv.second);
-    return m;
-  }
-  uint8_t* ptr(size_t off) const { return base_ + off; }
-  size_t used() const { return used_; }
-  size_t size() const { return size_; }
-
- private:
-  uint8_t* base_ = nullptr;
-  size_t size_ = 0, used_ = 0;
-  std::map<size_t, size_t> free_, live_;
-};
-
-struct SceneRec {
-  size_t off = SIZE_MAX;
-  SceneDev dev{};
-};
-
-// One launch of ds_optimize_seeds / traced: its tables live until every
-// problem in it is released.
-struct LaunchRec {
-  size_t tab_off = SIZE_MAX;   // ProbDev[n] + TileDev[nt] + counter
-  hipEvent_t done = nullptr;
-  int refs = 0;
-};
-
-struct ProblemRec {
-  int32_t tag;
-  int S, T;
-  size_t state_off = SIZE_MAX;   // tile states
-  size_t out_off = SIZE_MAX;     // seed results + result + final trajectories
-  ds_seed_result* seed_res = nullptr;
-  ds_result* result = nullptr;
-  float* final_traj = nullptr;
-  std::shared_ptr<LaunchRec> launch;
-};
-
-struct ServeReq;
-
-}  // namespace
-
-struct ds_plan {
-  int device = 0;
-  Arena arena;
-  size_t robot_off = SIZE_MAX, params_off = SIZE_MAX;
-  RobotDev robot{};
-  ParamsDev params{};
-  const RobotDev* robot_dev = nullptr;
-  const ParamsDev* params_dev = nullptr;
-  std::map<int32_t, SceneRec> scenes;
-  std::map<int32_t, ProblemRec> problems;
-  // deferred arena frees, each guarded by an event
-  std::vector<std::pair<hipEvent_t, size_t>> deferred;
-  std::vector<hipEvent_t> event_pool;
-  // pinned staging for table uploads
-  uint8_t* staging = nullptr;
-  size_t staging_cap = 0, staging_pos = 0;
-  std::vector<hipEvent_t> staging_events;
-  int cu_count = 0, blocks_per_cu = 1;
-  // optional kernel timing: (start, stop) event pairs not yet read
-  bool timing = false;
-  std::vector<std::pair<hipEvent_t, hipEvent_t>> timed;
-  // serving
-  struct Serve* serve = nullptr;
-};
-
-namespace {
 
 hipEvent_t get_event(ds_plan* p) {
   if (!p->event_pool.empty()) {
@@ -272,9 +143,15 @@ ProbDev make_probdev(ds_plan* p, const ds_problem& pr) {
   return d;
 }
 
+// Problem outputs: [seed results][result (256 B)][best trajectory (2 KiB)]
+// [final trajectories S x T x 7].
 size_t out_bytes(int S, int T) {
-  return ((size_t)S * sizeof(ds_seed_result) + 255) / 256 * 256 + 256 +
+  return ((size_t)S * sizeof(ds_seed_result) + 255) / 256 * 256 + 256 + 2048 +
          (size_t)S * T * NJ * sizeof(float);
+}
+
+double now_s() {
+  return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
 }
 
 int alloc_problem_outputs(ds_plan* p, ProblemRec& rec) {
@@ -285,7 +162,8 @@ int alloc_problem_outputs(ds_plan* p, ProblemRec& rec) {
   rec.seed_res = reinterpret_cast<ds_seed_result*>(base);
   size_t sr = ((size_t)rec.S * sizeof(ds_seed_result) + 255) / 256 * 256;
   rec.result = reinterpret_cast<ds_result*>(base + sr);
-  rec.final_traj = reinterpret_cast<float*>(base + sr + 256);
+  rec.best_traj = reinterpret_cast<float*>(base + sr + 256);
+  rec.final_traj = reinterpret_cast<float*>(base + sr + 256 + 2048);
   return DS_OK;
 }
 
@@ -301,27 +179,6 @@ void free_problem(ds_plan* p, ProblemRec& rec) {
     rec.launch.reset();
   }
 }
-
-}  // namespace
-
-// Launch `fn` on stream s, bracketed by timing events when enabled.
-template <class Fn>
-int timed_launch(ds_plan* p, hipStream_t s, Fn fn) {
-  hipEvent_t a = nullptr, b = nullptr;
-  if (p->timing) {
-    HIP_TRY(hipEventCreate(&a));
-    HIP_TRY(hipEventCreate(&b));
-    HIP_TRY(hipEventRecord(a, s));
-  }
-  HIP_TRY(fn());
-  if (p->timing) {
-    HIP_TRY(hipEventRecord(b, s));
-    p->timed.emplace_back(a, b);
-  }
-  return DS_OK;
-}
-
-namespace {
 
 int tiles_for(int S, int T) {
   int per = WAVE / group_size(T);
@@ -381,6 +238,7 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
     pd[i].final_traj = rec.final_traj;
     pd[i].seed_res = rec.seed_res;
     pd[i].result = rec.result;
+    pd[i].best_traj = rec.best_traj;
     if (n == 1) {
       pd[i].tr_x = tr_x; pd[i].tr_g = tr_g; pd[i].tr_J = tr_J; pd[i].tr_d = tr_d; pd[i].tr_a = tr_a;
     }
@@ -413,7 +271,7 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
                                blocks, p->params.n_iters, s);
       }))
     return rc;
-  HIP_TRY(launch_best(pd_dev, n, s));
+  HIP_TRY(launch_best(pd_dev, n, nullptr, s));
   launch->done = get_event(p);
   if (!launch->done) return fail(DS_ERR_HIP, "event creation failed");
   HIP_TRY(hipEventRecord(launch->done, s));
@@ -425,7 +283,9 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   return DS_OK;
 }
 
-}  // namespace
+}  // namespace dsh
+
+using namespace dsh;
 
 // ====================================================================== ABI ==
 extern "C" {
@@ -604,8 +464,8 @@ int ds_get_best(ds_plan* p, int32_t tag, float* traj_host, ds_result* out) {
   HIP_TRY(hipEventSynchronize(r.launch->done));
   HIP_TRY(hipMemcpy(out, r.result, sizeof(ds_result), hipMemcpyDeviceToHost));
   if (traj_host && out->best_seed >= 0)
-    HIP_TRY(hipMemcpy(traj_host, r.final_traj + (size_t)out->best_seed * r.T * NJ,
-                      (size_t)r.T * NJ * sizeof(float), hipMemcpyDeviceToHost));
+    HIP_TRY(hipMemcpy(traj_host, r.best_traj, (size_t)r.T * NJ * sizeof(float),
+                      hipMemcpyDeviceToHost));
   return DS_OK;
 }
 

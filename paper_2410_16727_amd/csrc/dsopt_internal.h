@@ -52,6 +52,7 @@ struct ProbDev {
   float* final_traj;     // arena [S][T][7]
   ds_seed_result* seed_res;   // arena [S]
   ds_result* result;          // arena
+  float* best_traj;           // arena [T][7], the best seed's trajectory
   float *tr_x, *tr_g, *tr_J, *tr_d, *tr_a;   // trace buffers or null
 };
 
@@ -98,7 +99,7 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
                            int max_iters, hipStream_t s);
-hipError_t launch_best(const ProbDev* probs, int n_probs, hipStream_t s);
+hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s);
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
                        int with_grad, hipStream_t s);

@@ -653,8 +653,10 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
 
 // Best seed per problem: lowest cost among successful seeds (ties: lowest
 // index), else lowest cost among valid seeds.
-__global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs) {
-  const ProbDev& pb = probs[blockIdx.x];
+__global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
+                                              const int* __restrict__ list) {
+  if (list && (int)blockIdx.x >= list[0]) return;
+  const ProbDev& pb = probs[list ? list[1 + blockIdx.x] : blockIdx.x];
   __shared__ int s_any;
   __shared__ unsigned long long s_key[2];
   __shared__ int s_valid;
@@ -673,10 +675,13 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs)
     }
   }
   __syncthreads();
+  const unsigned long long key = s_any ? s_key[1] : s_key[0];
+  const int best = (key == ~0ull) ? -1 : (int)(key & 0xffffffffu);
+  if (best >= 0)
+    for (int e = threadIdx.x; e < pb.T * NJ; e += blockDim.x)
+      pb.best_traj[e] = pb.final_traj[(size_t)best * pb.T * NJ + e];
   if (threadIdx.x == 0) {
     ds_result out;
-    unsigned long long key = s_any ? s_key[1] : s_key[0];
-    int best = (key == ~0ull) ? -1 : (int)(key & 0xffffffffu);
     out.best_seed = best;
     out.n_valid_seeds = s_valid;
     out.n_iters = pb.n_iters;
@@ -819,8 +824,8 @@ hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const Prob
   return hipGetLastError();
 }
 
-hipError_t launch_best(const ProbDev* probs, int n_probs, hipStream_t s) {
-  hipLaunchKernelGGL(k_best, dim3(n_probs), dim3(256), 0, s, probs);
+hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s) {
+  hipLaunchKernelGGL(k_best, dim3(n_probs), dim3(256), 0, s, probs, list);
   return hipGetLastError();
 }
 
