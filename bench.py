@@ -177,6 +177,96 @@ def run_batched(args, dsopt, torch, configs, params):
     return out
 
 
+def run_serving(args, dsopt, torch, configs, params):
+    """Poisson arrivals of mixed requests over 16 resident scenes: the
+    served (continuous batching, graph-captured blocks) form vs the plain
+    serial form (FIFO, one request at a time, one launch each)."""
+    key = "E"
+    w = configs.WORKLOADS[key]
+    robot = configs.robot(key)
+    t0 = time.perf_counter()
+    scenes = configs.scenes(key, threads=host_threads())
+    log(f"[bench] serving: built {len(scenes)} grids in {time.perf_counter() - t0:.1f} s")
+    pool = configs.problems(key)
+    trace = configs.serving_trace(args.serve_requests)
+    N = w.iters
+    cells = sum((s.dims[0] - 1) * (s.dims[1] - 1) * (s.dims[2] - 1) for s in scenes)
+    plan = dsopt.Plan(robot, params.DEFAULT, N, cells * 32 + (3 << 30), block_iters=10)
+    for i, sc in enumerate(scenes):
+        plan.upload_scene(i, sc.grid, sc.voxel, sc.origin)
+        sc.grid = None
+    reqs = []
+    for r, (arr, pi, S, T) in enumerate(trace):
+        p = pool[pi]
+        sd = torch.from_numpy(configs.seeds_for(key, pi, p, S=S, T=T, stream=r)).cuda()
+        reqs.append({"arrival": arr, "S": S, "T": T,
+                     "spec": {"scene": p.scene, "q_start": p.q_start, "goal": p.goal,
+                              "seeds": sd}})
+    torch.cuda.synchronize()
+    warm = min(200, len(reqs) // 10)
+
+    def summarize(lat, done_t, name):
+        lat = np.array(lat[warm:])
+        span = max(done_t[warm:]) - reqs[warm]["arrival"]
+        out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+               "mean_ms": float(lat.mean()), "max_ms": float(lat.max()),
+               "problems_per_s": float(len(lat) / span), "measured_requests": int(len(lat))}
+        log(f"[bench] serving {name}: p50 {out['p50_ms']:.2f} ms p99 {out['p99_ms']:.2f} ms "
+            f"{out['problems_per_s']:.1f} problems/s")
+        return out
+
+    # served form
+    plan.serve_start(max_slots=args.serve_slots, queue_cap=len(reqs) + 1)
+    lat = [0.0] * len(reqs)
+    done_t = [0.0] * len(reqs)
+    pending = {}
+    i = 0
+    n_done = 0
+    start = time.perf_counter()
+    while n_done < len(reqs):
+        now = time.perf_counter() - start
+        while i < len(reqs) and reqs[i]["arrival"] <= now:
+            pending[plan.serve_submit(reqs[i]["spec"])] = i
+            i += 1
+        active = plan.serve_step()
+        for t, r in list(pending.items()):
+            res = plan.serve_poll(t)
+            if res is not None:
+                tt = time.perf_counter() - start
+                lat[r] = (tt - reqs[r]["arrival"]) * 1e3
+                done_t[r] = tt
+                del pending[t]
+                n_done += 1
+        if active == 0 and not pending and i < len(reqs):
+            time.sleep(max(0.0, reqs[i]["arrival"] - (time.perf_counter() - start)))
+    stats = plan.serve_stats()
+    plan.serve_stop()
+    served = summarize(lat, done_t, "served")
+    served["mean_active_slots"] = stats["mean_active_slots"]
+    served["graph_replays"] = stats["steps"]
+    # plain serial form
+    lat = [0.0] * len(reqs)
+    done_t = [0.0] * len(reqs)
+    start = time.perf_counter()
+    for r, rq in enumerate(reqs):
+        now = time.perf_counter() - start
+        if rq["arrival"] > now:
+            time.sleep(rq["arrival"] - now)
+        plan.optimize([dict(rq["spec"], tag=r + 1)])
+        plan.get_best(r + 1, rq["T"])
+        plan.release(r + 1)
+        tt = time.perf_counter() - start
+        lat[r] = (tt - rq["arrival"]) * 1e3
+        done_t[r] = tt
+    plain = summarize(lat, done_t, "plain serial")
+    plan.close()
+    return {"workload": (f"serving: Poisson {len(reqs)} requests at 200/s ({warm} warm-up), "
+                         f"seeds U{{8..128}}, horizons U{{32..64}}, 16 resident 200^3 ESDFs, "
+                         f"{N} iters, blocks of 10 iterations per graph replay, "
+                         f"{args.serve_slots} slots"),
+            "served": served, "plain_serial": plain}
+
+
 def cpu_baseline(single, params, configs):
     """The FP64 oracle on the same problem, all host threads, ~10 s."""
     import oracle
@@ -211,6 +301,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2200)
+    ap.add_argument("--serve-slots", type=int, default=64)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this path has no multi-GPU form); got "
@@ -254,6 +347,8 @@ def main():
     }
     if not args.no_batched:
         rec["batched"] = run_batched(args, dsopt, torch, configs, params)
+    if not args.no_serving:
+        rec["serving"] = run_serving(args, dsopt, torch, configs, params)
     if not args.no_cpu_baseline:
         rec["cpu_baseline"] = cpu_baseline(single, params, configs)
     print(json.dumps(rec), flush=True)
