@@ -26,6 +26,33 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ["paper_2410_16727_amd/csrc/dsopt_kernels.hip",
+                  "paper_2410_16727_amd/csrc/dsopt_internal.h"]
+PMC_SUMMARY = "profiles/k_optimize_pmc_cluttered.json"
+COPY_BYTES = 256 << 20
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def measured_traffic():
+    """HBM bytes per optimiser launch from the committed rocprofv3 PMC
+    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors),
+    or None when the kernel source changed since the counters were taken."""
+    path = os.path.join(ROOT, PMC_SUMMARY)
+    if not os.path.exists(path):
+        return None, None
+    with open(path) as f:
+        rec = json.load(f)
+    if rec.get("kernel_source_sha256") != kernel_source_hash():
+        return None, rec
+    return rec.get("traffic_bytes_per_launch"), rec
 
 
 def log(*a):
@@ -58,7 +85,8 @@ def run_single(args, dsopt, torch, configs, params):
     S, T, N = prob.S, prob.T, w.iters
     log(f"[bench] workload {key} ({w.name}): S={S} T={T} spheres={robot.n_spheres} "
         f"grid={scene.dims} iters={N}")
-    plan = dsopt.Plan(robot, params.DEFAULT, N, 1 << 30)
+    prm = dict(params.DEFAULT, waves_per_seed=args.waves)
+    plan = dsopt.Plan(robot, prm, N, 1 << 30)
     plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
     seeds = torch.from_numpy(configs.seeds_for(key, 0, prob)).cuda()
     out = torch.zeros_like(seeds)
@@ -121,7 +149,7 @@ def run_batched(args, dsopt, torch, configs, params):
     state = sum(((p.S + per(p.T) - 1) // per(p.T)) * 40 * 1024 + p.S * p.T * 28 + p.S * 64
                 for p in probs)
     arena = cells * 32 + 2 * state + (512 << 20)
-    plan = dsopt.Plan(robot, params.DEFAULT, N, arena)
+    plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.batched_waves), N, arena)
     for i, sc in enumerate(scenes):
         plan.upload_scene(i, sc.grid, sc.voxel, sc.origin)
         sc.grid = None
@@ -191,7 +219,8 @@ def run_serving(args, dsopt, torch, configs, params):
     trace = configs.serving_trace(args.serve_requests)
     N = w.iters
     cells = sum((s.dims[0] - 1) * (s.dims[1] - 1) * (s.dims[2] - 1) for s in scenes)
-    plan = dsopt.Plan(robot, params.DEFAULT, N, cells * 32 + (3 << 30), block_iters=10)
+    plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.serve_waves), N,
+                      cells * 32 + (3 << 30), block_iters=10)
     for i, sc in enumerate(scenes):
         plan.upload_scene(i, sc.grid, sc.voxel, sc.origin)
         sc.grid = None
@@ -299,9 +328,17 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="B", choices=["A", "B", "C"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--waves", type=int, default=8,
+                    help="wavefronts per seed for the single-problem workload")
+    ap.add_argument("--batched-waves", type=int, default=1,
+                    help="wavefronts per seed for the batched workload")
+    ap.add_argument("--serve-waves", type=int, default=1,
+                    help="wavefronts per seed for the serving workload")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="run one 256 MiB device copy (known traffic) for PMC scaling")
     ap.add_argument("--serve-requests", type=int, default=2200)
     ap.add_argument("--serve-slots", type=int, default=64)
     args = ap.parse_args()
@@ -317,7 +354,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dsopt.load()
+    if args.calibrate_copy:
+        a = torch.empty(COPY_BYTES // 4, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
     single = run_single(args, dsopt, torch, configs, params)
+    traffic, pmc = measured_traffic()
     S, T, N = single["S"], single["T"], single["N"]
     value = S * T * N / (single["ms_per_step"] / 1e3)
     rec = {
@@ -336,11 +381,12 @@ def main():
         "config": {"workload": f"cluttered: 1 problem, {S} seeds x {T} waypoints, "
                                f"{single['spheres']} spheres, {single['grid'][0]}^3 FP32 ESDF "
                                f"at 1 cm, {N} L-BFGS iters",
-                   "seeds": S, "horizon": T, "iters": N, "spheres": single["spheres"]},
+                   "seeds": S, "horizon": T, "iters": N, "spheres": single["spheres"],
+                   "waves_per_seed": args.waves},
         "problems_per_s": 1e3 / single["ms_per_step"],
         "roofline": {"bound": "hbm", "kernel": "k_optimize",
                      "achieved": single["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": single["achieved_gbs"] / HBM_PEAK_GBS, "traffic": None,
+                     "frac": single["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_ms": single["kernel_ms"],
                      "algorithmic_bytes_per_launch": single["gather_bytes"],
                      "evals_per_seed": single["evals_per_seed"]},

@@ -100,6 +100,10 @@ typedef struct ds_params {
   float tol_rot;       /* success threshold on rotation error, radians (Sec. 5.1: 2.86 deg) */
   int32_t n_iters;     /* iterations per optimisation (Sec. 4.4, N_iters) */
   int32_t block_iters; /* iterations per serving step (graph replay) */
+  int32_t waves_per_seed; /* 1, 2, 4 or 8 wavefronts cooperate on one seed: more
+                             parallelism per seed for latency-bound launches (few
+                             seeds); results depend on it only through the
+                             order of floating-point sums */
 } ds_params;
 
 /* One planning problem (Sec. 3).  `seeds` are the seed trajectories

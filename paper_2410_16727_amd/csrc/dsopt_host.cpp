@@ -180,9 +180,10 @@ void free_problem(ds_plan* p, ProblemRec& rec) {
   }
 }
 
+// One wavefront per seed: the 64/G lanes of a waypoint split its spheres.
 int tiles_for(int S, int T) {
-  int per = WAVE / group_size(T);
-  return (S + per - 1) / per;
+  (void)T;
+  return S;
 }
 
 // Build and launch one optimisation over problems[0..n).
@@ -242,12 +243,11 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
     if (n == 1) {
       pd[i].tr_x = tr_x; pd[i].tr_g = tr_g; pd[i].tr_J = tr_J; pd[i].tr_d = tr_d; pd[i].tr_a = tr_a;
     }
-    int per = WAVE / pd[i].G;
     for (int k = 0; k < nt; ++k) {
       TileDev t{};
       t.prob = i;
-      t.seed0 = k * per;
-      t.nseed = std::min(per, rec.S - k * per);
+      t.seed0 = k;
+      t.nseed = 1;
       t.G = pd[i].G;
       t.state = reinterpret_cast<float*>(p->arena.ptr(rec.state_off) + (size_t)k * ST_BYTES);
       td.push_back(t);
@@ -263,12 +263,13 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   if (int rc = upload(p, pd_dev, pd.data(), n * sizeof(ProbDev), s)) return rc;
   if (int rc = upload(p, td_dev, td.data(), td.size() * sizeof(TileDev), s)) return rc;
   HIP_TRY(launch_zero_i32(counter, 1, s));
-  int waves_needed = total_tiles;
-  int blocks = (waves_needed + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  const int W = p->params.waves;
+  const int per_block = W > 1 ? 1 : WAVES_PER_BLOCK;
+  int blocks = (total_tiles + per_block - 1) / per_block;
   blocks = std::max(1, std::min(blocks, p->cu_count * p->blocks_per_cu));
   if (int rc = timed_launch(p, s, [&]() {
         return launch_optimize(p->robot_dev, p->params_dev, pd_dev, td_dev, total_tiles, counter,
-                               blocks, p->params.n_iters, s);
+                               blocks, p->params.n_iters, W, s);
       }))
     return rc;
   HIP_TRY(launch_best(pd_dev, n, nullptr, s));
@@ -314,7 +315,9 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   }
   if (!(prm->eps > 0) || prm->history < 1 || prm->history > DS_MAX_HISTORY || prm->n_ls < 1 ||
       prm->n_ls > DS_MAX_LS || prm->n_iters < 0 || prm->block_iters < 1 || !(prm->dt > 0) ||
-      !(prm->delta0 > 0) || !(prm->step_max > 0))
+      !(prm->delta0 > 0) || !(prm->step_max > 0) ||
+      !(prm->waves_per_seed == 1 || prm->waves_per_seed == 2 || prm->waves_per_seed == 4 ||
+        prm->waves_per_seed == 8))
     return fail(DS_ERR_INVALID, "invalid parameters");
 
   auto p = std::make_unique<ds_plan>();
@@ -322,7 +325,7 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
   p->cu_count = prop.multiProcessorCount;
-  p->blocks_per_cu = 2;
+  p->blocks_per_cu = optimize_blocks_per_cu(prm->waves_per_seed);
   p->arena.init(static_cast<uint8_t*>(arena_dev), arena_bytes);
 
   RobotDev& rb = p->robot;
@@ -356,6 +359,7 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   P.c1 = prm->c1; P.delta0 = prm->delta0; P.dmax = prm->step_max; P.dt = prm->dt;
   P.tol_pos = prm->tol_pos; P.tol_rot = prm->tol_rot;
   P.m = prm->history; P.nls = prm->n_ls; P.n_iters = prm->n_iters; P.block_iters = prm->block_iters;
+  P.waves = prm->waves_per_seed;
 
   p->robot_off = p->arena.alloc(sizeof(RobotDev));
   p->params_off = p->arena.alloc(sizeof(ParamsDev));

@@ -29,6 +29,7 @@ struct ParamsDev {
   float lv, la, lj, wp, wr, wl;
   float c1, delta0, dmax, dt, tol_pos, tol_rot;
   int32_t m, nls, n_iters, block_iters;
+  int32_t waves;         // wavefronts per seed (1, 2, 4 or 8)
 };
 
 // One resident scene: the 8 corners of cell (i,j,k) are the 32-byte record
@@ -58,9 +59,9 @@ struct ProbDev {
 
 struct TileDev {
   int32_t prob;          // index into the problem table
-  int32_t seed0;         // first seed of the tile
-  int32_t nseed;         // seeds in the tile (1..64/G)
-  int32_t G;
+  int32_t seed0;         // the tile's seed
+  int32_t nseed;         // 1: one seed per wavefront
+  int32_t G;             // lanes per copy of the trajectory (64/G copies split the spheres)
   float* state;          // tile state (layout below)
 };
 
@@ -98,7 +99,7 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
                             hipStream_t s);
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
-                           int max_iters, hipStream_t s);
+                           int max_iters, int waves, hipStream_t s);
 hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s);
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
@@ -108,5 +109,8 @@ hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, floa
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
 hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                              const TileDev* tiles, const int* tile_list, int* counter,
-                             int max_tiles, int grid_blocks, int max_iters, hipStream_t s);
+                             int max_tiles, int grid_blocks, int max_iters, int waves,
+                             hipStream_t s);
+int team_block(int waves);
+int optimize_blocks_per_cu(int waves);
 }  // namespace dsk

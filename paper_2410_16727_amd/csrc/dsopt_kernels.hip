@@ -26,19 +26,44 @@ namespace dsk {
 namespace {
 
 constexpr unsigned RSRC_DWORD3 = 0x00020000u;   // raw buffer, gfx9 family
+#ifndef DSOPT_CH
+#define DSOPT_CH 2
+#endif
+constexpr int CH = DSOPT_CH;                     // sphere gathers in flight per lane
 
-__device__ __forceinline__ float grp_sum(float v, int G) {
-  for (int off = 1; off < G; off <<= 1) v += __shfl_xor(v, off);
+// Butterfly reductions over a lane group of G = 16, 32 or 64 lanes.  The
+// first four stages pair lanes inside a 16-lane row with DPP (quad
+// permutations 1<->0 / 2<->0, then the half-row and row mirrors), the
+// remaining ones with cross-row shuffles.  Every pairing is an involution,
+// so both partners add the same two numbers and every lane of the group ends
+// with bitwise the same result.
+constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1,0,3,2]
+constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2,3,0,1]
+constexpr int DPP_HALF_MIRROR = 0x141;
+constexpr int DPP_MIRROR = 0x140;
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+struct OpSum { __device__ static float f(float a, float b) { return a + b; } };
+struct OpMax { __device__ static float f(float a, float b) { return fmaxf(a, b); } };
+struct OpMin { __device__ static float f(float a, float b) { return fminf(a, b); } };
+
+template <class Op>
+__device__ __forceinline__ float grp_reduce(float v, int G) {
+  v = Op::f(v, dpp<DPP_QUAD_XOR1>(v));
+  v = Op::f(v, dpp<DPP_QUAD_XOR2>(v));
+  v = Op::f(v, dpp<DPP_HALF_MIRROR>(v));
+  v = Op::f(v, dpp<DPP_MIRROR>(v));
+  for (int off = 16; off < G; off <<= 1) v = Op::f(v, __shfl_xor(v, off));
   return v;
 }
-__device__ __forceinline__ float grp_max(float v, int G) {
-  for (int off = 1; off < G; off <<= 1) v = fmaxf(v, __shfl_xor(v, off));
-  return v;
-}
-__device__ __forceinline__ float grp_min(float v, int G) {
-  for (int off = 1; off < G; off <<= 1) v = fminf(v, __shfl_xor(v, off));
-  return v;
-}
+__device__ __forceinline__ float grp_sum(float v, int G) { return grp_reduce<OpSum>(v, G); }
+__device__ __forceinline__ float grp_max(float v, int G) { return grp_reduce<OpMax>(v, G); }
+__device__ __forceinline__ float grp_min(float v, int G) { return grp_reduce<OpMin>(v, G); }
 __device__ __forceinline__ float dot7(const float* a, const float* b) {
   float s = a[0] * b[0];
 #pragma unroll
@@ -67,7 +92,7 @@ __device__ __forceinline__ Goal make_goal(const ProbDev& pb) {
 struct Sampler {
   __amdgpu_buffer_rsrc_t rsrc;
   float ox, oy, oz, inv_h, nxm1, nym1, nzm1;
-  int nxm2, nym2, nzm2, cx, cxy;   // cells along x, cells in an x-y layer
+  int nxm2, nym2, nzm2, cx, cy;    // cells along x and y
 };
 
 __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
@@ -77,56 +102,90 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
   s.nxm1 = (float)(sc.nx - 1); s.nym1 = (float)(sc.ny - 1); s.nzm1 = (float)(sc.nz - 1);
   s.nxm2 = sc.nx - 2; s.nym2 = sc.ny - 2; s.nzm2 = sc.nz - 2;
   s.cx = sc.nx - 1;
-  s.cxy = (sc.nx - 1) * (sc.ny - 1);
+  s.cy = sc.ny - 1;
   return s;
 }
 
-// Trilinear distance at p (clamped into the grid) and, with GRAD, its
-// spatial gradient (zero along clamped axes).  Cell along an axis is
-// min(floor(u), n-2) with u = (p - origin) / voxel.
-template <bool GRAD>
-__device__ __forceinline__ float sample(const Sampler& S, float px, float py, float pz, float& gx,
-                                        float& gy, float& gz) {
+// Cell lookup for a query point: clamp u = (p - origin) / voxel into the
+// grid, cell min(floor(u), n-2) per axis, fractional position, and which
+// axes were inside (gradient is zero along clamped axes).
+struct Cell {
+  int off;            // byte offset of the cell's 32-byte record
+  float fx, fy, fz;
+  float mx, my, mz;   // 1/voxel inside the grid along the axis, 0 when clamped
+};
+
+__device__ __forceinline__ Cell locate(const Sampler& S, float px, float py, float pz) {
+  Cell c;
   float ux = (px - S.ox) * S.inv_h;
   float uy = (py - S.oy) * S.inv_h;
   float uz = (pz - S.oz) * S.inv_h;
-  bool inx = ux >= 0.f && ux <= S.nxm1;
-  bool iny = uy >= 0.f && uy <= S.nym1;
-  bool inz = uz >= 0.f && uz <= S.nzm1;
-  ux = fminf(fmaxf(ux, 0.f), S.nxm1);
-  uy = fminf(fmaxf(uy, 0.f), S.nym1);
-  uz = fminf(fmaxf(uz, 0.f), S.nzm1);
+  float cx = fminf(fmaxf(ux, 0.f), S.nxm1);
+  float cy = fminf(fmaxf(uy, 0.f), S.nym1);
+  float cz = fminf(fmaxf(uz, 0.f), S.nzm1);
+  c.mx = (cx == ux) ? S.inv_h : 0.f;
+  c.my = (cy == uy) ? S.inv_h : 0.f;
+  c.mz = (cz == uz) ? S.inv_h : 0.f;
+  ux = cx;
+  uy = cy;
+  uz = cz;
   int ix = min((int)ux, S.nxm2);
   int iy = min((int)uy, S.nym2);
   int iz = min((int)uz, S.nzm2);
-  float fx = ux - (float)ix, fy = uy - (float)iy, fz = uz - (float)iz;
-  int rec = ix + S.cx * iy + S.cxy * iz;
-  int off = rec * 32;
-  auto va = __builtin_amdgcn_raw_buffer_load_b128(S.rsrc, off, 0, 0);
-  auto vb = __builtin_amdgcn_raw_buffer_load_b128(S.rsrc, off + 16, 0, 0);
-  float4 a = *reinterpret_cast<float4*>(&va);   // z0: c000 c100 c010 c110
-  float4 b = *reinterpret_cast<float4*>(&vb);   // z1: c001 c101 c011 c111
+  c.fx = ux - (float)ix;
+  c.fy = uy - (float)iy;
+  c.fz = uz - (float)iz;
+  // record index ix + cx*(iy + cy*iz); every factor fits 24 bits
+  unsigned row = __umul24((unsigned)S.cy, (unsigned)iz) + (unsigned)iy;
+  c.off = (int)((__umul24((unsigned)S.cx, row) + (unsigned)ix) << 5);
+  return c;
+}
+
+// Trilinear blend of a cell record (a: z0 corners, b: z1 corners) and, with
+// GRAD, its spatial gradient.
+template <bool GRAD>
+__device__ __forceinline__ float blend(const Sampler& S, const Cell& c, float4 a, float4 b,
+                                       float& gx, float& gy, float& gz) {
   float dx00 = a.y - a.x, dx10 = a.w - a.z, dx01 = b.y - b.x, dx11 = b.w - b.z;
-  float c00 = a.x + fx * dx00;
-  float c10 = a.z + fx * dx10;
-  float c01 = b.x + fx * dx01;
-  float c11 = b.z + fx * dx11;
+  float c00 = a.x + c.fx * dx00;
+  float c10 = a.z + c.fx * dx10;
+  float c01 = b.x + c.fx * dx01;
+  float c11 = b.z + c.fx * dx11;
   float dy0 = c10 - c00, dy1 = c11 - c01;
-  float c0 = c00 + fy * dy0;
-  float c1 = c01 + fy * dy1;
+  float c0 = c00 + c.fy * dy0;
+  float c1 = c01 + c.fy * dy1;
   float dz = c1 - c0;
-  float d = c0 + fz * dz;
+  float d = c0 + c.fz * dz;
   if (GRAD) {
-    float e0 = dx00 + fy * (dx10 - dx00);
-    float e1 = dx01 + fy * (dx11 - dx01);
-    gx = inx ? (e0 + fz * (e1 - e0)) * S.inv_h : 0.f;
-    gy = iny ? (dy0 + fz * (dy1 - dy0)) * S.inv_h : 0.f;
-    gz = inz ? dz * S.inv_h : 0.f;
+    float e0 = dx00 + c.fy * (dx10 - dx00);
+    float e1 = dx01 + c.fy * (dx11 - dx01);
+    gx = (e0 + c.fz * (e1 - e0)) * c.mx;
+    gy = (dy0 + c.fz * (dy1 - dy0)) * c.my;
+    gz = dz * c.mz;
   }
   return d;
 }
 
+__device__ __forceinline__ float4 load_rec(const Sampler& S, int off) {
+  auto v = __builtin_amdgcn_raw_buffer_load_b128(S.rsrc, off, 0, 0);
+  return *reinterpret_cast<float4*>(&v);
+}
+
 enum { EV_COST = 0, EV_GRAD = 1, EV_RESULT = 2 };
+
+// Joint twists (axis z_i, origin o_i) of the swept joints, kept for the
+// wrench projections of the adjoint.
+struct Twists {
+  float z[NJ][3], o[NJ][3];
+  __device__ __forceinline__ void put(int i, const float* R, const float* p) {
+    z[i][0] = R[2]; z[i][1] = R[5]; z[i][2] = R[8];
+    o[i][0] = p[0]; o[i][1] = p[1]; o[i][2] = p[2];
+  }
+  __device__ __forceinline__ void get(int i, float* zi, float* oi) const {
+    zi[0] = z[i][0]; zi[1] = z[i][1]; zi[2] = z[i][2];
+    oi[0] = o[i][0]; oi[1] = o[i][1]; oi[2] = o[i][2];
+  }
+};
 
 struct EvalOut {
   float cost;        // this lane's share of the seed objective (0 when inactive)
@@ -167,18 +226,42 @@ __device__ __forceinline__ float smoothness(const ParamsDev& P, const float* q, 
   return c;
 }
 
+// A team of W wavefronts (one workgroup) optimises one seed: every
+// wavefront holds the whole trajectory (one waypoint per lane group) and
+// takes every (W*L)-th sphere of each link; the partial sums meet in
+// double-buffered LDS with one barrier per evaluation.  W = 1: independent
+// wavefronts, no barrier.
+constexpr int MAX_TEAM = 8;
+constexpr int PART = NJ + 2;   // partial sums per lane: hinge sum, gradient row, clearance
+
+struct Team {
+  int W, w;       // team size, this wavefront's index
+  float* lds;     // [2][W][PART][64]
+  int buf;
+  __device__ __forceinline__ void sync() const {
+    if (W > 1) __syncthreads();
+  }
+};
+
 // One evaluation of the objective at this lane's configuration q.
 template <int MODE>
 __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
                                             const ParamsDev& P, const Sampler& S, const Goal& goal,
-                                            const float* q, int t, int T, bool active) {
+                                            const float* q, int t, int T, int G, bool active,
+                                            Team& tm) {
   constexpr bool GRAD = (MODE == EV_GRAD);
+  // the L = 64/G lanes holding the same waypoint in each of the W
+  // wavefronts split its spheres: copy index and stride
+  const int L = WAVE / G;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int cp = tm.w * L + lane / G;
+  const int LW = tm.W * L;
   EvalOut o;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) o.g[j] = 0.f;
   float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
   float p[3] = {0.f, 0.f, 0.f};
-  float zs[NJ][3], os[NJ][3];
+  Twists tw;
   float phisum = 0.f, clr = FLT_MAX;
 #pragma unroll
   for (int l = 0; l < NJ; ++l) {
@@ -201,45 +284,108 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       R[3 * r + 2] = A[3 * r + 2];
       p[r] = pa[r];
     }
-    if (GRAD) {
-      zs[l][0] = R[2]; zs[l][1] = R[5]; zs[l][2] = R[8];
-      os[l][0] = p[0]; os[l][1] = p[1]; os[l][2] = p[2];
-    }
+    if (GRAD) tw.put(l, R, p);
     float Fx = 0.f, Fy = 0.f, Fz = 0.f, Mx = 0.f, My = 0.f, Mz = 0.f;
     const int s0 = rb->link_begin[l], s1 = rb->link_begin[l + 1];
-#pragma unroll 2
-    for (int s = s0; s < s1; ++s) {
-      float4 sp = rb->sph[s];
-      float cx = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
-      float cy = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
-      float cz = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
-      float gx, gy, gz;
-      float d = sample<GRAD>(S, cx, cy, cz, gx, gy, gz);
-      float D = d - sp.w;
-      float De = D - P.eps;
-      float phi = (D < 0.f) ? (0.5f * P.eps - D) : ((D < P.eps) ? De * De * P.half_inv_eps : 0.f);
-      phisum += phi;
-      if (MODE == EV_RESULT) clr = fminf(clr, D);
-      if (GRAD) {
-        float dphi = (D < 0.f) ? -1.f : ((D < P.eps) ? De * P.inv_eps : 0.f);
-        float w = P.wc * dphi;
-        float fx = w * gx, fy = w * gy, fz = w * gz;
-        Fx += fx; Fy += fy; Fz += fz;
-        Mx += cy * fz - cz * fy;
-        My += cz * fx - cx * fz;
-        Mz += cx * fy - cy * fx;
+    // chunks of CH spheres per lane (this lane takes every L-th sphere of
+    // the link): issue every record load of the chunk, then consume them in
+    // sphere order -- CH gathers in flight per lane
+    for (int s = s0; s < s1; s += LW * CH) {
+      Cell cl[CH];
+      float4 ra[CH], rz[CH];
+      float cxs[CH], cys[CH], czs[CH], rr[CH];
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        const int sk = s + k * LW + cp;
+        if (sk < s1) {
+          float4 sp = rb->sph[sk];
+          cxs[k] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
+          cys[k] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
+          czs[k] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
+          rr[k] = sp.w;
+          cl[k] = locate(S, cxs[k], cys[k], czs[k]);
+          ra[k] = load_rec(S, cl[k].off);
+          rz[k] = load_rec(S, cl[k].off + 16);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < CH; ++k) {
+        if (s + k * LW + cp < s1) {
+          float gx, gy, gz;
+          float d = blend<GRAD>(S, cl[k], ra[k], rz[k], gx, gy, gz);
+          float D = d - rr[k];
+          float De = D - P.eps;
+          float phi = (D < P.eps) ? De * De * P.half_inv_eps : 0.f;
+          phi = (D < 0.f) ? 0.5f * P.eps - D : phi;
+          phisum += phi;
+          if (MODE == EV_RESULT) clr = fminf(clr, D);
+          if (GRAD) {
+            float dphi = (D < P.eps) ? De * P.inv_eps : 0.f;
+            dphi = (D < 0.f) ? -1.f : dphi;
+            float w = P.wc * dphi;
+            float fx = w * gx, fy = w * gy, fz = w * gz;
+            Fx += fx; Fy += fy; Fz += fz;
+            Mx += cys[k] * fz - czs[k] * fy;
+            My += czs[k] * fx - cxs[k] * fz;
+            Mz += cxs[k] * fy - cys[k] * fx;
+          }
+        }
       }
     }
     if (GRAD) {
       // wrench of link l+1 on every joint i <= l: z_i . (M - o_i x F)
 #pragma unroll
       for (int i = 0; i <= l; ++i) {
-        float tx = Mx - (os[i][1] * Fz - os[i][2] * Fy);
-        float ty = My - (os[i][2] * Fx - os[i][0] * Fz);
-        float tz = Mz - (os[i][0] * Fy - os[i][1] * Fx);
-        o.g[i] += zs[i][0] * tx + zs[i][1] * ty + zs[i][2] * tz;
+        float zi[3], oi[3];
+        if (i == l) {
+          zi[0] = R[2]; zi[1] = R[5]; zi[2] = R[8];
+          oi[0] = p[0]; oi[1] = p[1]; oi[2] = p[2];
+        } else {
+          tw.get(i, zi, oi);
+        }
+        float tx = Mx - (oi[1] * Fz - oi[2] * Fy);
+        float ty = My - (oi[2] * Fx - oi[0] * Fz);
+        float tz = Mz - (oi[0] * Fy - oi[1] * Fx);
+        o.g[i] += zi[0] * tx + zi[1] * ty + zi[2] * tz;
       }
     }
+  }
+  // sum the sphere shares of the L lanes of this waypoint (butterfly: every
+  // copy ends with the same value)
+  for (int off = G; off < WAVE; off <<= 1) {
+    phisum += __shfl_xor(phisum, off);
+    if (MODE == EV_RESULT) clr = fminf(clr, __shfl_xor(clr, off));
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) o.g[j] += __shfl_xor(o.g[j], off);
+    }
+  }
+  if (tm.W > 1) {
+    // ... and of the W wavefronts, summed in wavefront order
+    float* mine = tm.lds + ((tm.buf * tm.W + tm.w) * PART) * WAVE + lane;
+    mine[0] = phisum;
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) mine[(1 + j) * WAVE] = o.g[j];
+    }
+    if (MODE == EV_RESULT) mine[(1 + NJ) * WAVE] = clr;
+    tm.sync();
+    const float* all = tm.lds + (tm.buf * tm.W * PART) * WAVE + lane;
+    phisum = all[0];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j)
+      if (GRAD) o.g[j] = all[(1 + j) * WAVE];
+    if (MODE == EV_RESULT) clr = all[(1 + NJ) * WAVE];
+    for (int v = 1; v < tm.W; ++v) {
+      const float* pv = all + v * PART * WAVE;
+      phisum += pv[0];
+      if (GRAD) {
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) o.g[j] += pv[(1 + j) * WAVE];
+      }
+      if (MODE == EV_RESULT) clr = fminf(clr, pv[(1 + NJ) * WAVE]);
+    }
+    tm.buf ^= 1;
   }
   // end effector and goal pose
   const float* E = rb->Fee;
@@ -271,11 +417,13 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     float fx = k2 * ex, fy = k2 * ey, fz = k2 * ez;
 #pragma unroll
     for (int i = 0; i < NJ; ++i) {
-      float rx = pe[0] - os[i][0], ry = pe[1] - os[i][1], rz = pe[2] - os[i][2];
+      float zi[3], oi[3];
+      tw.get(i, zi, oi);
+      float rx = pe[0] - oi[0], ry = pe[1] - oi[1], rz = pe[2] - oi[2];
       float tx = ry * fz - rz * fy + k4 * wx;
       float ty = rz * fx - rx * fz + k4 * wy;
       float tz = rx * fy - ry * fx + k4 * wz;
-      o.g[i] += zs[i][0] * tx + zs[i][1] * ty + zs[i][2] * tz;
+      o.g[i] += zi[0] * tx + zi[1] * ty + zi[2] * tz;
     }
   }
   if (MODE == EV_RESULT) {
@@ -320,8 +468,9 @@ struct TileCtx {
   Sampler S;
   Goal goal;
   float* st;
-  int lane, G, t, T, seed, gi;
-  bool valid, active;
+  int lane, G, t, T, seed;
+  bool owner;    // first copy of the waypoint: writes outputs and traces
+  bool active;   // t < T
 };
 
 __device__ __forceinline__ float* col(float* st, int base, int j, int lane) {
@@ -412,19 +561,19 @@ __device__ __forceinline__ void direction(const TileCtx& c, const float* g, int&
 }
 
 __device__ __forceinline__ void trace_row(float* buf, const TileCtx& c, int k, const float* v) {
-  if (!buf || !c.valid || c.t >= c.T) return;
+  if (!buf || !c.owner || c.t >= c.T) return;
   size_t base = (((size_t)k * c.pb->S + c.seed) * c.T + c.t) * NJ;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) buf[base + j] = v[j];
 }
 __device__ __forceinline__ void trace_scalar(float* buf, const TileCtx& c, int k, float v) {
-  if (!buf || !c.valid || c.t != 0) return;
+  if (!buf || !c.owner || c.t != 0) return;
   buf[(size_t)k * c.pb->S + c.seed] = v;
 }
 
 // Final per-seed results and output trajectory.
-__device__ void finalize(const TileCtx& c, const float* x, float J) {
-  EvalOut r = evaluate<EV_RESULT>(c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.active);
+__device__ void finalize(const TileCtx& c, const float* x, Team& tm) {
+  EvalOut r = evaluate<EV_RESULT>(c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.G, c.active, tm);
   float Jr = grp_sum(r.cost, c.G);
   float clr = grp_min(c.active ? r.clr : FLT_MAX, c.G);
   float perr = grp_sum((c.t == c.T - 1) ? r.perr : 0.f, c.G);
@@ -442,7 +591,7 @@ __device__ void finalize(const TileCtx& c, const float* x, float J) {
     jm = fmaxf(jm, (c.t + 3 < c.T) ? fabsf(v) : 0.f);
   }
   jm = grp_max(jm, c.G);
-  if (c.valid && c.t < c.T) {
+  if (c.owner && c.t < c.T) {
     float* ft = c.pb->final_traj + ((size_t)c.seed * c.T + c.t) * NJ;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) ft[j] = x[j];
@@ -452,7 +601,7 @@ __device__ void finalize(const TileCtx& c, const float* x, float J) {
       for (int j = 0; j < NJ; ++j) ot[j] = x[j];
     }
   }
-  if (c.valid && c.t == 0) {
+  if (c.owner && c.t == 0) {
     ds_seed_result sr;
     sr.cost = Jr;
     sr.clearance = clr;
@@ -470,12 +619,21 @@ __device__ void finalize(const TileCtx& c, const float* x, float J) {
     sr.pad = 0;
     c.pb->seed_res[c.seed] = sr;
   }
-  (void)J;
 }
 
+enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
+
 // Run up to max_iters iterations of one tile (state persists in the arena).
+// The wavefront loops over phases around a single cost+gradient evaluation:
+//   INIT   evaluate the seed (first launch of the tile only);
+//   DIR    direction from the history, trial point x + d;
+//   TRIAL  Armijo test of alpha = 1 (its gradient is already there); further
+//          cost-only candidates while a seed of the tile has no Armijo step;
+//          if a seed accepted alpha < 1, evaluate there (ACCEPT), else update;
+//   ACCEPT take the accepted point's cost and gradient, update.
 __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
-                         const ProbDev* __restrict__ probs, const TileDev& td, int max_iters) {
+                         const ProbDev* __restrict__ probs, const TileDev& td, int max_iters,
+                         Team& tm) {
   TileCtx c;
   c.rb = rb;
   c.P = *pp;
@@ -486,34 +644,31 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
   c.lane = threadIdx.x & (WAVE - 1);
   c.G = td.G;
   c.t = c.lane & (c.G - 1);
-  c.gi = c.lane / c.G;
   c.T = c.pb->T;
-  c.seed = td.seed0 + c.gi;
-  c.valid = c.gi < td.nseed;
-  c.active = c.valid && c.t < c.T;
+  c.seed = td.seed0;
+  c.owner = tm.w == 0 && c.lane < c.G;
+  c.active = c.t < c.T;
+  const bool writer = tm.w == 0;   // the team's first wavefront writes state
   const int n_iters = c.pb->n_iters;
   int* sti = reinterpret_cast<int*>(c.st);
+  const ProbDev& pb = *c.pb;
 
-  float x[NJ], g[NJ], J;
-  int cnt, head, iter, evc, evg;
-  iter = sti[ST_ITER + c.lane];
+  float x[NJ], g[NJ], d[NJ], xe[NJ], gt[NJ];
+  float J = 0.f, Jt = 0.f, gtd = 0.f, alpha = 0.f;
+  int cnt, head, evc, evg, chosen = 0;
+  int iter = sti[ST_ITER + c.lane];
+  int phase;
   if (iter == 0) {
     if (c.active) {
-      const float* sp = c.pb->seeds + ((size_t)c.seed * c.T + c.t) * NJ;
+      const float* sp = pb.seeds + ((size_t)c.seed * c.T + c.t) * NJ;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) x[j] = (c.t == 0) ? c.pb->qs[j] : sp[j];
+      for (int j = 0; j < NJ; ++j) xe[j] = (c.t == 0) ? pb.qs[j] : sp[j];
     } else {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) x[j] = 0.f;
+      for (int j = 0; j < NJ; ++j) xe[j] = 0.f;
     }
-    EvalOut e = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, x, c.t, c.T, c.active);
-    J = grp_sum(e.cost, c.G);
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) g[j] = e.g[j];
-    cnt = 0;
-    head = 0;
-    evc = 0;
-    evg = 1;
+    cnt = head = evc = evg = 0;
+    phase = PH_INIT;
   } else {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -525,65 +680,82 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
     head = sti[ST_HEAD + c.lane];
     evc = sti[ST_EVC + c.lane];
     evg = sti[ST_EVG + c.lane];
+    phase = PH_DIR;
   }
-  const int n_run = min(max_iters, n_iters - iter);
-  const ProbDev& pb = *c.pb;
-  for (int k = 0; k < n_run; ++k, ++iter) {
-    trace_row(pb.tr_x, c, iter, x);
-    trace_row(pb.tr_g, c, iter, g);
-    trace_scalar(pb.tr_J, c, iter, J);
-    float d[NJ];
-    direction(c, g, cnt, head, d);
-    trace_row(pb.tr_d, c, iter, d);
-    const float gtd = grp_sum(dot7(g, d), c.G);
-    // candidate alpha = 1 with its gradient
-    float xt[NJ];
+  int n_left = min(max_iters, n_iters - iter);
+
+  for (;;) {
+    if (phase == PH_DIR) {
+      if (n_left <= 0) break;
+      trace_row(pb.tr_x, c, iter, x);
+      trace_row(pb.tr_g, c, iter, g);
+      trace_scalar(pb.tr_J, c, iter, J);
+      direction(c, g, cnt, head, d);
+      trace_row(pb.tr_d, c, iter, d);
+      gtd = grp_sum(dot7(g, d), c.G);
 #pragma unroll
-    for (int j = 0; j < NJ; ++j) xt[j] = x[j] + d[j];
-    EvalOut e = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, xt, c.t, c.T, c.active);
-    ++evg;
-    float Jt = grp_sum(e.cost, c.G);
-    float gt[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) gt[j] = e.g[j];
-    int chosen = (Jt <= J + c.P.c1 * gtd) ? 0 : -1;
-    float Jmin = Jt;
-    int kmin = 0;
-    for (int kk = 1; kk < c.P.nls; ++kk) {
-      bool need = chosen < 0;
-      if (!__any(need)) break;
-      float al = ldexpf(1.f, -kk);
-      float xk[NJ];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) xk[j] = x[j] + al * d[j];
-      EvalOut ek = evaluate<EV_COST>(rb, c.P, c.S, c.goal, xk, c.t, c.T, c.active);
-      ++evc;
-      float Jk = grp_sum(ek.cost, c.G);
-      if (need && Jk <= J + c.P.c1 * al * gtd) chosen = kk;
-      if (need && Jk < Jmin) { Jmin = Jk; kmin = kk; }
+      for (int j = 0; j < NJ; ++j) xe[j] = x[j] + d[j];
+      phase = PH_TRIAL;
     }
-    if (chosen < 0 && Jmin < J) chosen = kmin;
-    const float alpha = chosen >= 0 ? ldexpf(1.f, -chosen) : 0.f;
-    if (__any(chosen > 0)) {
-      float al = chosen > 0 ? alpha : 1.f;
-      float xa[NJ];
+    // the one cost+gradient evaluation of this pass
+    EvalOut e = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, xe, c.t, c.T, c.G, c.active, tm);
+    ++evg;
+    const float Je = grp_sum(e.cost, c.G);
+    if (phase == PH_INIT) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) xa[j] = x[j] + al * d[j];
-      EvalOut ea = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, xa, c.t, c.T, c.active);
-      ++evg;
-      float Ja = grp_sum(ea.cost, c.G);
+      for (int j = 0; j < NJ; ++j) { x[j] = xe[j]; g[j] = e.g[j]; }
+      J = Je;
+      phase = PH_DIR;
+      continue;
+    }
+    bool update_now = true;
+    if (phase == PH_TRIAL) {
+      Jt = Je;
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) gt[j] = e.g[j];
+      chosen = (Jt <= J + c.P.c1 * gtd) ? 0 : -1;
+      float Jmin = Jt;
+      int kmin = 0;
+      for (int kk = 1; kk < c.P.nls; ++kk) {
+        bool need = chosen < 0;
+        if (!__any(need)) break;
+        float al = ldexpf(1.f, -kk);
+        float xk[NJ];
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) xk[j] = x[j] + al * d[j];
+        EvalOut ek = evaluate<EV_COST>(rb, c.P, c.S, c.goal, xk, c.t, c.T, c.G, c.active, tm);
+        ++evc;
+        float Jk = grp_sum(ek.cost, c.G);
+        if (need && Jk <= J + c.P.c1 * al * gtd) chosen = kk;
+        if (need && Jk < Jmin) { Jmin = Jk; kmin = kk; }
+      }
+      if (chosen < 0 && Jmin < J) chosen = kmin;
+      alpha = chosen >= 0 ? ldexpf(1.f, -chosen) : 0.f;
+      if (__any(chosen > 0)) {
+        // evaluate the accepted step (seeds that took alpha = 1 recompute
+        // the same point and keep their trial values)
+        float al = chosen > 0 ? alpha : 1.f;
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) xe[j] = x[j] + al * d[j];
+        phase = PH_ACCEPT;
+        update_now = false;
+      }
+    } else {   // PH_ACCEPT
       if (chosen > 0) {
-        Jt = Ja;
+        Jt = Je;
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) { gt[j] = ea.g[j]; xt[j] = xa[j]; }
+        for (int j = 0; j < NJ; ++j) gt[j] = e.g[j];
       }
     }
+    if (!update_now) continue;
+    // history update and step
     trace_scalar(pb.tr_a, c, iter, alpha);
     const bool accept = chosen >= 0;
     float s[NJ], y[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      s[j] = accept ? xt[j] - x[j] : 0.f;
+      float xn = x[j] + alpha * d[j];
+      s[j] = accept ? xn - x[j] : 0.f;
       y[j] = accept ? gt[j] - g[j] : 0.f;
     }
     float sy = grp_sum(dot7(s, y), c.G);
@@ -591,63 +763,88 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
     float yy = grp_sum(dot7(y, y), c.G);
     if (accept) {
       if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy)) {
+        if (writer) {
 #pragma unroll
-        for (int j = 0; j < NJ; ++j) {
-          *col(c.st, ST_S + head * NJ * WAVE, j, c.lane) = s[j];
-          *col(c.st, ST_Y + head * NJ * WAVE, j, c.lane) = y[j];
+          for (int j = 0; j < NJ; ++j) {
+            *col(c.st, ST_S + head * NJ * WAVE, j, c.lane) = s[j];
+            *col(c.st, ST_Y + head * NJ * WAVE, j, c.lane) = y[j];
+          }
+          c.st[ST_RHO + head * WAVE + c.lane] = 1.f / sy;
+          c.st[ST_YY + head * WAVE + c.lane] = yy;
         }
-        c.st[ST_RHO + head * WAVE + c.lane] = 1.f / sy;
-        c.st[ST_YY + head * WAVE + c.lane] = yy;
         head = (head + 1) % c.P.m;
         cnt = min(cnt + 1, c.P.m);
       }
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) { x[j] = xt[j]; g[j] = gt[j]; }
+      for (int j = 0; j < NJ; ++j) { x[j] = x[j] + alpha * d[j]; g[j] = gt[j]; }
       J = Jt;
     } else {
       cnt = 0;
     }
+    ++iter;
+    --n_left;
+    phase = PH_DIR;
+    tm.sync();   // the writer's history is visible to the team
   }
   // persist the state
+  if (writer) {
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    *col(c.st, ST_X, j, c.lane) = x[j];
-    *col(c.st, ST_G, j, c.lane) = g[j];
-  }
-  c.st[ST_J + c.lane] = J;
-  sti[ST_CNT + c.lane] = cnt;
-  sti[ST_HEAD + c.lane] = head;
-  sti[ST_ITER + c.lane] = iter;
-  sti[ST_EVC + c.lane] = evc;
-  sti[ST_EVG + c.lane] = evg;
-  if (iter == n_iters && n_run >= 0) {
-    if (n_run > 0 || max_iters >= 0) {
-      trace_row(pb.tr_x, c, iter, x);
-      trace_row(pb.tr_g, c, iter, g);
-      trace_scalar(pb.tr_J, c, iter, J);
+    for (int j = 0; j < NJ; ++j) {
+      *col(c.st, ST_X, j, c.lane) = x[j];
+      *col(c.st, ST_G, j, c.lane) = g[j];
     }
-    finalize(c, x, J);
+    c.st[ST_J + c.lane] = J;
+    sti[ST_CNT + c.lane] = cnt;
+    sti[ST_HEAD + c.lane] = head;
+    sti[ST_ITER + c.lane] = iter;
+    sti[ST_EVC + c.lane] = evc;
+    sti[ST_EVG + c.lane] = evg;
+  }
+  if (iter == n_iters) {
+    trace_row(pb.tr_x, c, iter, x);
+    trace_row(pb.tr_g, c, iter, g);
+    trace_scalar(pb.tr_J, c, iter, J);
+    finalize(c, x, tm);
   }
 }
 
 // Persistent optimiser: every wavefront takes tiles from an atomic counter
 // until the table is exhausted (tile_list, if given, indirects the table;
 // n_tiles_dev, if given, overrides n_tiles).
-__global__ void __launch_bounds__(BLOCK)
+// Persistent optimiser: every team (W = 1: every wavefront) takes tiles
+// from an atomic counter until the table is exhausted (tile_list, if given,
+// indirects the table; n_tiles_dev, if given, overrides n_tiles).  Every
+// member of a team sees the same tile sequence and the same decisions, so
+// all of them reach every barrier.
+__global__ void __launch_bounds__(MAX_TEAM * WAVE)
 k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
            const ProbDev* __restrict__ probs, const TileDev* __restrict__ tiles,
            const int* __restrict__ tile_list, const int* __restrict__ n_tiles_dev, int n_tiles,
            int* counter, int max_iters) {
+  extern __shared__ float s_dyn[];
+  __shared__ int s_tile;
   const int lane = threadIdx.x & (WAVE - 1);
   const int nt = n_tiles_dev ? *n_tiles_dev : n_tiles;
+  Team tm;
+  tm.W = pp->waves;
+  tm.w = (tm.W > 1) ? (int)(threadIdx.x / WAVE) : 0;
+  tm.lds = s_dyn;
+  tm.buf = 0;
   for (;;) {
     int mine = 0;
-    if (lane == 0) mine = atomicAdd(counter, 1);
-    mine = __builtin_amdgcn_readfirstlane(__shfl(mine, 0));
+    if (tm.W > 1) {
+      if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+      __syncthreads();
+      mine = s_tile;
+      __syncthreads();
+    } else {
+      if (lane == 0) mine = atomicAdd(counter, 1);
+      mine = __builtin_amdgcn_readfirstlane(__shfl(mine, 0));
+    }
     if (mine >= nt) break;
     const int ti = tile_list ? tile_list[mine] : mine;
     TileDev td = tiles[ti];
-    run_tile(rb, pp, probs, td, max_iters);
+    run_tile(rb, pp, probs, td, max_iters, tm);
   }
 }
 
@@ -711,32 +908,36 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
        int with_grad) {
   const int lane = threadIdx.x & (WAVE - 1);
-  const int wave = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
-  const int per = WAVE / G;
-  const int gi = lane / G, t = lane & (G - 1);
-  const int seed = wave * per + gi;
-  if (wave * per >= S) return;   // whole wavefront past the end
-  const bool active = seed < S && t < T;
+  const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+  if (seed >= S) return;   // whole wavefront past the end
+  const int t = lane & (G - 1);
+  const bool owner = lane < G;
+  const bool active = t < T;
   ParamsDev P = *pp;
   Sampler Sm = make_sampler(pb->sc);
   Goal goal = make_goal(*pb);
+  Team tm;
+  tm.W = 1;
+  tm.w = 0;
+  tm.lds = nullptr;
+  tm.buf = 0;
   float x[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) x[j] = active ? X[((size_t)seed * T + t) * NJ + j] : 0.f;
   float J;
   if (with_grad) {
-    EvalOut e = evaluate<EV_GRAD>(rb, P, Sm, goal, x, t, T, active);
+    EvalOut e = evaluate<EV_GRAD>(rb, P, Sm, goal, x, t, T, G, active, tm);
     J = grp_sum(e.cost, G);
-    float w = (dJ && seed < S) ? dJ[seed] : 1.f;
-    if (active) {
+    float w = dJ ? dJ[seed] : 1.f;
+    if (active && owner) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) dX[((size_t)seed * T + t) * NJ + j] = w * e.g[j];
     }
   } else {
-    EvalOut e = evaluate<EV_COST>(rb, P, Sm, goal, x, t, T, active);
+    EvalOut e = evaluate<EV_COST>(rb, P, Sm, goal, x, t, T, G, active, tm);
     J = grp_sum(e.cost, G);
   }
-  if (J_out && seed < S && t == 0) J_out[seed] = J;
+  if (J_out && lane == 0) J_out[seed] = J;
 }
 
 // Sphere centres (parity dump), one thread per seed-waypoint.
@@ -807,21 +1008,35 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
   return hipGetLastError();
 }
 
+int team_block(int W) { return (W > 1 ? W : WAVES_PER_BLOCK) * WAVE; }
+size_t team_lds(int W) { return W > 1 ? (size_t)2 * W * PART * WAVE * sizeof(float) : 0; }
+
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
-                           int max_iters, hipStream_t s) {
-  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(BLOCK), 0, s, rb, pp, probs, tiles,
+                           int max_iters, int W, hipStream_t s) {
+  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(team_block(W)), team_lds(W), s, rb, pp,
+                     probs, tiles,
                      (const int*)nullptr, (const int*)nullptr, n_tiles, counter, max_iters);
   return hipGetLastError();
 }
 
 hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                              const TileDev* tiles, const int* tile_list, int* counter,
-                             int max_tiles, int grid_blocks, int max_iters, hipStream_t s) {
+                             int max_tiles, int grid_blocks, int max_iters, int W,
+                             hipStream_t s) {
   // tile_list[0] holds the number of listed tiles, the indices follow
-  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(BLOCK), 0, s, rb, pp, probs, tiles,
+  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(team_block(W)), team_lds(W), s, rb, pp,
+                     probs, tiles,
                      tile_list + 1, tile_list, max_tiles, counter, max_iters);
   return hipGetLastError();
+}
+
+int optimize_blocks_per_cu(int W) {
+  int n = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_optimize, team_block(W), team_lds(W)) !=
+      hipSuccess)
+    return 1;
+  return n > 0 ? n : 1;
 }
 
 hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s) {
@@ -833,9 +1048,7 @@ hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* p
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
                        int with_grad, hipStream_t s) {
   int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
-  int per = WAVE / G;
-  int waves = (S + per - 1) / per;
-  int blocks = (waves + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  int blocks = (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, dJ,
                      J_out, dX, with_grad);
   return hipGetLastError();

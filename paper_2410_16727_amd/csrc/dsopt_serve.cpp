@@ -163,11 +163,10 @@ int admit(ds_plan* p, Serve* sv) {
     pd.result = rec.result;
     pd.best_traj = rec.best_traj;
     std::vector<TileDev> td(nt);
-    int per = WAVE / pd.G;
     for (int k = 0; k < nt; ++k) {
       td[k].prob = slot;
-      td[k].seed0 = k * per;
-      td[k].nseed = std::min(per, pr.n_seeds - k * per);
+      td[k].seed0 = k;
+      td[k].nseed = 1;
       td[k].G = pd.G;
       td[k].state = reinterpret_cast<float*>(p->arena.ptr(rec.state_off) + (size_t)k * ST_BYTES);
     }
@@ -239,7 +238,7 @@ int ds_serve_start(ds_plan* p, int max_slots, int queue_cap, void* stream) {
   hipError_t e1 = launch_zero_i32(sv->counter_dev, 1, sv->stream);
   hipError_t e2 = launch_serve_step(p->robot_dev, p->params_dev, sv->probs_dev, sv->tiles_dev,
                                     sv->tile_list_dev, sv->counter_dev, (int)max_tiles, grid,
-                                    p->params.block_iters, sv->stream);
+                                    p->params.block_iters, p->params.waves, sv->stream);
   hipError_t e3 = launch_best(sv->probs_dev, max_slots, sv->slot_list_dev, sv->stream);
   hipError_t e4 = hipStreamEndCapture(sv->stream, &sv->graph);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {

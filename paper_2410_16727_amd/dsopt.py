@@ -12,7 +12,8 @@ import os
 import numpy as np
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libdsopt.so")
+# DSOPT_LIB selects another build of the same library (e.g. a tuning variant)
+LIB_PATH = os.environ.get("DSOPT_LIB") or os.path.join(HERE, "libdsopt.so")
 
 DS_OK = 0
 DS_ERR_INVALID = -1
@@ -57,7 +58,8 @@ class Params(C.Structure):
                 ("w_rot", C.c_float), ("w_limit", C.c_float), ("history", C.c_int32),
                 ("n_ls", C.c_int32), ("c1", C.c_float), ("delta0", C.c_float),
                 ("step_max", C.c_float), ("dt", C.c_float), ("tol_pos", C.c_float),
-                ("tol_rot", C.c_float), ("n_iters", C.c_int32), ("block_iters", C.c_int32)]
+                ("tol_rot", C.c_float), ("n_iters", C.c_int32), ("block_iters", C.c_int32),
+                ("waves_per_seed", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -174,6 +176,7 @@ def params_struct(p: dict, n_iters: int, block_iters: int = 10):
     s.c1 = p["c1"]; s.delta0 = p["delta0"]; s.step_max = p["step_max"]; s.dt = p["dt"]
     s.tol_pos = p["tol_pos"]; s.tol_rot = p["tol_rot"]
     s.n_iters = int(n_iters); s.block_iters = int(block_iters)
+    s.waves_per_seed = int(p.get("waves_per_seed", 1))
     return s
 
 

@@ -33,13 +33,13 @@ def say(*a):
 
 
 class Setup:
-    def __init__(self, key, iters=None):
+    def __init__(self, key, iters=None, waves=1):
         self.key = key
         self.robot = configs.robot(key)
         self.scene = configs.scenes(key, only={0})[0]
         self.prob = configs.problems(key)[0]
         self.iters = iters if iters is not None else configs.WORKLOADS[key].iters
-        self.plan = dsopt.Plan(self.robot, P, self.iters, 512 << 20)
+        self.plan = dsopt.Plan(self.robot, dict(P, waves_per_seed=waves), self.iters, 512 << 20)
         self.plan.upload_scene(0, self.scene.grid, self.scene.voxel, self.scene.origin)
         self.O = oracle.Oracle(self.robot, self.scene, params.as_list(), threads=8)
 
@@ -47,10 +47,10 @@ class Setup:
 _setups = {}
 
 
-def setup(key, iters=None):
-    k = (key, iters)
+def setup(key, iters=None, waves=1):
+    k = (key, iters, waves)
     if k not in _setups:
-        _setups[k] = Setup(key, iters)
+        _setups[k] = Setup(key, iters, waves)
     return _setups[k]
 
 
@@ -148,17 +148,17 @@ def lockstep_check(su, tr, S):
     return ties
 
 
-@pytest.mark.parametrize("key", ["A", "B"])
-def test_lockstep_iterations(key):
-    su = setup(key)
+@pytest.mark.parametrize("key,waves", [("A", 1), ("B", 1), ("A", 8), ("B", 8), ("B", 2)])
+def test_lockstep_iterations(key, waves):
+    su = setup(key, waves=waves)
     seeds, tr = run_traced(su)
     lockstep_check(su, tr, seeds.shape[0])
     su.plan.release(7)
 
 
-@pytest.mark.parametrize("key", ["A", "B"])
-def test_flags_match_oracle_on_final_trajectories(key):
-    su = setup(key)
+@pytest.mark.parametrize("key,waves", [("A", 1), ("B", 1), ("B", 8)])
+def test_flags_match_oracle_on_final_trajectories(key, waves):
+    su = setup(key, waves=waves)
     seeds, tr = run_traced(su, tag=8)
     S, T = seeds.shape[0], seeds.shape[1]
     res = su.plan.seed_results(8, S)
@@ -199,11 +199,12 @@ def test_invalid_inputs_are_rejected():
         su.plan.upload_scene(3, np.zeros((1, 4, 4), dtype=np.float32), 0.1, (0, 0, 0))
 
 
-def test_determinism_bitwise():
-    su = setup("B")
+@pytest.mark.parametrize("waves", [1, 4])
+def test_determinism_bitwise(waves):
+    su = setup("B", waves=waves)
     seeds = torch.from_numpy(configs.seeds_for("B", 0, su.prob)).cuda()
     outs = []
-    for tag in (21, 22):
+    for tag in (21 + 10 * waves, 22 + 10 * waves):
         out = torch.zeros_like(seeds)
         su.plan.optimize([{"scene": 0, "q_start": su.prob.q_start, "goal": su.prob.goal,
                            "seeds": seeds, "tag": tag, "out": out}])

@@ -50,6 +50,38 @@ def spec(p, seeds, tag, out=None):
             "out": out}
 
 
+def test_team_launch_batched_equals_plain_bitwise():
+    """With 4 wavefronts per seed: batched == plain bitwise, and the final
+    per-seed costs and flags agree with the FP64 oracle evaluated on the
+    final trajectories."""
+    key = "D"
+    robot = configs.robot(key)
+    probs = configs.problems(key)[:6]
+    scenes = configs.scenes(key, only=set(p.scene for p in probs))
+    pl = dsopt.Plan(robot, dict(P, waves_per_seed=4), 40, 512 << 20)
+    for p in probs:
+        sc = scenes[p.scene]
+        pl.upload_scene(p.scene, sc.grid, sc.voxel, sc.origin)
+    seeds = [torch.from_numpy(configs.seeds_for(key, i, p)).cuda() for i, p in enumerate(probs)]
+    ob = [torch.zeros_like(sd) for sd in seeds]
+    op = [torch.zeros_like(sd) for sd in seeds]
+    say("team launch (4 wavefronts per seed): batched vs plain")
+    pl.optimize([spec(p, seeds[i], 700 + i, ob[i]) for i, p in enumerate(probs)])
+    for i, p in enumerate(probs):
+        pl.optimize([spec(p, seeds[i], 800 + i, op[i])])
+    torch.cuda.synchronize()
+    for i, p in enumerate(probs):
+        assert torch.equal(ob[i], op[i]), i
+        res = pl.seed_results(700 + i, p.S)
+        O = oracle.Oracle(robot, scenes[p.scene], params.as_list(), threads=8)
+        ref = O.results(p.q_start, p.goal, ob[i].cpu().numpy().astype(np.float64))
+        assert (np.abs(res["cost"] - ref["J"]) / ref["J"]).max() < 1e-4, i
+        amb = np.abs(ref["clearance"]) < 1e-5
+        for f in ["collision_free", "success", "valid"]:
+            assert ((res[f] == ref[f].astype(int)) | amb).all(), (i, f)
+    pl.close()
+
+
 def test_batched_equals_plain_bitwise(batchD):
     plan, probs, seeds = batchD["plan"], batchD["probs"], batchD["seeds"]
     idx = list(range(0, 64, 4))       # 16 problems, mixed S and T
