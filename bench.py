@@ -221,9 +221,9 @@ def run_serving(args, dsopt, torch, configs, params):
     cells = sum((s.dims[0] - 1) * (s.dims[1] - 1) * (s.dims[2] - 1) for s in scenes)
     plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.serve_waves), N,
                       cells * 32 + (3 << 30), block_iters=10)
+    grids = [sc.grid for sc in scenes]
     for i, sc in enumerate(scenes):
         plan.upload_scene(i, sc.grid, sc.voxel, sc.origin)
-        sc.grid = None
     reqs = []
     for r, (arr, pi, S, T) in enumerate(trace):
         p = pool[pi]
@@ -273,7 +273,13 @@ def run_serving(args, dsopt, torch, configs, params):
     served = summarize(lat, done_t, "served")
     served["mean_active_slots"] = stats["mean_active_slots"]
     served["graph_replays"] = stats["steps"]
-    # plain serial form
+    # plain serial form: FIFO, one request at a time, each one launch, on a
+    # plan with its own best (latency) team size
+    plan.close()
+    plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.serve_plain_waves), N,
+                      cells * 32 + (3 << 30), block_iters=10)
+    for i, g in enumerate(grids):
+        plan.upload_scene(i, g, scenes[i].voxel, scenes[i].origin)
     lat = [0.0] * len(reqs)
     done_t = [0.0] * len(reqs)
     start = time.perf_counter()
@@ -292,7 +298,8 @@ def run_serving(args, dsopt, torch, configs, params):
     return {"workload": (f"serving: Poisson {len(reqs)} requests at 200/s ({warm} warm-up), "
                          f"seeds U{{8..128}}, horizons U{{32..64}}, 16 resident 200^3 ESDFs, "
                          f"{N} iters, blocks of 10 iterations per graph replay, "
-                         f"{args.serve_slots} slots"),
+                         f"{args.serve_slots} slots; served form {args.serve_waves} and plain "
+                         f"serial form {args.serve_plain_waves} wavefronts per seed"),
             "served": served, "plain_serial": plain}
 
 
@@ -333,7 +340,9 @@ def main():
     ap.add_argument("--batched-waves", type=int, default=1,
                     help="wavefronts per seed for the batched workload")
     ap.add_argument("--serve-waves", type=int, default=1,
-                    help="wavefronts per seed for the serving workload")
+                    help="wavefronts per seed for the served (batched) form")
+    ap.add_argument("--serve-plain-waves", type=int, default=8,
+                    help="wavefronts per seed for the plain serial form")
     ap.add_argument("--no-batched", action="store_true")
     ap.add_argument("--batched-steps", type=int, default=3)
     ap.add_argument("--no-serving", action="store_true")

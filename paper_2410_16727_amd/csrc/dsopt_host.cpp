@@ -344,6 +344,8 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
     while (cur < rb.ns && robot->spheres[order[cur]].link <= l) ++cur;
     rb.link_begin[l] = cur;   // spheres of link l+1 start here
   }
+  rb.max_per_link = 0;
+  for (int l = 0; l < 7; ++l) rb.max_per_link = std::max(rb.max_per_link, rb.link_begin[l + 1] - rb.link_begin[l]);
   for (int k = 0; k < rb.ns; ++k) {
     const ds_sphere& sp = robot->spheres[order[k]];
     rb.sph[k] = make_float4(sp.offset[0], sp.offset[1], sp.offset[2], sp.radius);

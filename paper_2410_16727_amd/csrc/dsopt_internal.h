@@ -19,6 +19,7 @@ struct RobotDev {
   float Fee[12];
   float qlo[7], qhi[7];
   int32_t ns;
+  int32_t max_per_link;              // most spheres on one link
   int32_t link_begin[8];             // spheres of link l (1..7): [link_begin[l-1], link_begin[l])
   float4 sph[DS_MAX_SPHERES];        // offset xyz, radius; sorted by link
   int32_t perm[DS_MAX_SPHERES];      // sorted position -> caller's sphere index

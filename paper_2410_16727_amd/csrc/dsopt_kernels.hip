@@ -243,8 +243,54 @@ struct Team {
   }
 };
 
-// One evaluation of the objective at this lane's configuration q.
+// Hinge cost of one sphere sample and, with GRAD, its force accumulated into
+// the link wrench (F, M about the world origin).
 template <int MODE>
+__device__ __forceinline__ void sphere_term(const ParamsDev& P, const Sampler& S, const Cell& cl,
+                                            float4 ra, float4 rz, float r, float cx, float cy,
+                                            float cz, float& phisum, float& clr, float* FM) {
+  constexpr bool GRAD = (MODE == EV_GRAD);
+  float gx, gy, gz;
+  float d = blend<GRAD>(S, cl, ra, rz, gx, gy, gz);
+  float D = d - r;
+  float De = D - P.eps;
+  float phi = (D < P.eps) ? De * De * P.half_inv_eps : 0.f;
+  phi = (D < 0.f) ? 0.5f * P.eps - D : phi;
+  phisum += phi;
+  if (MODE == EV_RESULT) clr = fminf(clr, D);
+  if (GRAD) {
+    float dphi = (D < P.eps) ? De * P.inv_eps : 0.f;
+    dphi = (D < 0.f) ? -1.f : dphi;
+    float w = P.wc * dphi;
+    float fx = w * gx, fy = w * gy, fz = w * gz;
+    FM[0] += fx; FM[1] += fy; FM[2] += fz;
+    FM[3] += cy * fz - cz * fy;
+    FM[4] += cz * fx - cx * fz;
+    FM[5] += cx * fy - cy * fx;
+  }
+}
+
+// Project a link wrench on the joints 0..l: g_i += z_i . (M - o_i x F).
+__device__ __forceinline__ void project(const Twists& tw, int l, const float* FM, float* g) {
+#pragma unroll
+  for (int i = 0; i < NJ; ++i) {
+    if (i > l) break;
+    float zi[3], oi[3];
+    tw.get(i, zi, oi);
+    float tx = FM[3] - (oi[1] * FM[2] - oi[2] * FM[1]);
+    float ty = FM[4] - (oi[2] * FM[0] - oi[0] * FM[2]);
+    float tz = FM[5] - (oi[0] * FM[1] - oi[1] * FM[0]);
+    g[i] += zi[0] * tx + zi[1] * ty + zi[2] * tz;
+  }
+}
+
+// One evaluation of the objective at this lane's configuration q.
+// PIPE (every lane holds at most one sphere of each link, W*L >= spheres
+// per link): the forward sweep issues each link's record load as soon as
+// its frame exists and the samples are consumed after the sweep, so one
+// memory round trip covers the whole evaluation.  Otherwise each link is
+// processed in chunks of CH gathers right after its frame.
+template <int MODE, bool PIPE>
 __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
                                             const ParamsDev& P, const Sampler& S, const Goal& goal,
                                             const float* q, int t, int T, int G, bool active,
@@ -263,6 +309,10 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   float p[3] = {0.f, 0.f, 0.f};
   Twists tw;
   float phisum = 0.f, clr = FLT_MAX;
+  // PIPE: the lane's sample of every link
+  float4 pa_[PIPE ? NJ : 1], pz_[PIPE ? NJ : 1];
+  float pc_[PIPE ? NJ : 1][3], pr_[PIPE ? NJ : 1];
+  bool pv_[PIPE ? NJ : 1];
 #pragma unroll
   for (int l = 0; l < NJ; ++l) {
     const float* F = rb->F[l];
@@ -285,11 +335,26 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       p[r] = pa[r];
     }
     if (GRAD) tw.put(l, R, p);
-    float Fx = 0.f, Fy = 0.f, Fz = 0.f, Mx = 0.f, My = 0.f, Mz = 0.f;
     const int s0 = rb->link_begin[l], s1 = rb->link_begin[l + 1];
-    // chunks of CH spheres per lane (this lane takes every L-th sphere of
-    // the link): issue every record load of the chunk, then consume them in
-    // sphere order -- CH gathers in flight per lane
+    if (PIPE) {
+      const int sk = s0 + cp;
+      pv_[l] = sk < s1;
+      if (pv_[l]) {
+        float4 sp = rb->sph[sk];
+        pc_[l][0] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
+        pc_[l][1] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
+        pc_[l][2] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
+        pr_[l] = sp.w;
+        Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
+        pa_[l] = load_rec(S, cl.off);
+        pz_[l] = load_rec(S, cl.off + 16);
+      }
+      continue;
+    }
+    float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    // chunks of CH spheres per lane (this lane takes every (W*L)-th sphere
+    // of the link): issue every record load of the chunk, then consume them
+    // in sphere order -- CH gathers in flight per lane
     for (int s = s0; s < s1; s += LW * CH) {
       Cell cl[CH];
       float4 ra[CH], rz[CH];
@@ -310,44 +375,23 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
-        if (s + k * LW + cp < s1) {
-          float gx, gy, gz;
-          float d = blend<GRAD>(S, cl[k], ra[k], rz[k], gx, gy, gz);
-          float D = d - rr[k];
-          float De = D - P.eps;
-          float phi = (D < P.eps) ? De * De * P.half_inv_eps : 0.f;
-          phi = (D < 0.f) ? 0.5f * P.eps - D : phi;
-          phisum += phi;
-          if (MODE == EV_RESULT) clr = fminf(clr, D);
-          if (GRAD) {
-            float dphi = (D < P.eps) ? De * P.inv_eps : 0.f;
-            dphi = (D < 0.f) ? -1.f : dphi;
-            float w = P.wc * dphi;
-            float fx = w * gx, fy = w * gy, fz = w * gz;
-            Fx += fx; Fy += fy; Fz += fz;
-            Mx += cys[k] * fz - czs[k] * fy;
-            My += czs[k] * fx - cxs[k] * fz;
-            Mz += cxs[k] * fy - cys[k] * fx;
-          }
-        }
+        if (s + k * LW + cp < s1)
+          sphere_term<MODE>(P, S, cl[k], ra[k], rz[k], rr[k], cxs[k], cys[k], czs[k], phisum,
+                            clr, FM);
       }
     }
-    if (GRAD) {
-      // wrench of link l+1 on every joint i <= l: z_i . (M - o_i x F)
+    if (GRAD) project(tw, l, FM, o.g);
+  }
+  if (PIPE) {
 #pragma unroll
-      for (int i = 0; i <= l; ++i) {
-        float zi[3], oi[3];
-        if (i == l) {
-          zi[0] = R[2]; zi[1] = R[5]; zi[2] = R[8];
-          oi[0] = p[0]; oi[1] = p[1]; oi[2] = p[2];
-        } else {
-          tw.get(i, zi, oi);
-        }
-        float tx = Mx - (oi[1] * Fz - oi[2] * Fy);
-        float ty = My - (oi[2] * Fx - oi[0] * Fz);
-        float tz = Mz - (oi[0] * Fy - oi[1] * Fx);
-        o.g[i] += zi[0] * tx + zi[1] * ty + zi[2] * tz;
+    for (int l = 0; l < NJ; ++l) {
+      float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      if (pv_[l]) {
+        Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
+        sphere_term<MODE>(P, S, cl, pa_[l], pz_[l], pr_[l], pc_[l][0], pc_[l][1], pc_[l][2],
+                          phisum, clr, FM);
       }
+      if (GRAD) project(tw, l, FM, o.g);
     }
   }
   // sum the sphere shares of the L lanes of this waypoint (butterfly: every
@@ -459,6 +503,21 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   return o;
 }
 
+// The evaluation form for this team: PIPE when every lane holds at most one
+// sphere per link.
+template <int MODE>
+__device__ __forceinline__ EvalOut eval_any(bool pipe, const RobotDev* __restrict__ rb,
+                                            const ParamsDev& P, const Sampler& S, const Goal& goal,
+                                            const float* q, int t, int T, int G, bool active,
+                                            Team& tm) {
+  if (pipe) return evaluate<MODE, true>(rb, P, S, goal, q, t, T, G, active, tm);
+  return evaluate<MODE, false>(rb, P, S, goal, q, t, T, G, active, tm);
+}
+
+__device__ __forceinline__ bool use_pipe(const RobotDev* __restrict__ rb, const Team& tm, int G) {
+  return tm.W * (WAVE / G) >= rb->max_per_link;
+}
+
 // ------------------------------------------------------------ optimiser ----
 
 struct TileCtx {
@@ -470,6 +529,7 @@ struct TileCtx {
   float* st;
   int lane, G, t, T, seed;
   bool owner;    // first copy of the waypoint: writes outputs and traces
+  bool pipe;     // all-gathers-in-flight evaluation form
   bool active;   // t < T
 };
 
@@ -573,7 +633,7 @@ __device__ __forceinline__ void trace_scalar(float* buf, const TileCtx& c, int k
 
 // Final per-seed results and output trajectory.
 __device__ void finalize(const TileCtx& c, const float* x, Team& tm) {
-  EvalOut r = evaluate<EV_RESULT>(c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.G, c.active, tm);
+  EvalOut r = eval_any<EV_RESULT>(c.pipe, c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.G, c.active, tm);
   float Jr = grp_sum(r.cost, c.G);
   float clr = grp_min(c.active ? r.clr : FLT_MAX, c.G);
   float perr = grp_sum((c.t == c.T - 1) ? r.perr : 0.f, c.G);
@@ -647,6 +707,7 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
   c.T = c.pb->T;
   c.seed = td.seed0;
   c.owner = tm.w == 0 && c.lane < c.G;
+  c.pipe = use_pipe(rb, tm, c.G);
   c.active = c.t < c.T;
   const bool writer = tm.w == 0;   // the team's first wavefront writes state
   const int n_iters = c.pb->n_iters;
@@ -698,7 +759,7 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
       phase = PH_TRIAL;
     }
     // the one cost+gradient evaluation of this pass
-    EvalOut e = evaluate<EV_GRAD>(rb, c.P, c.S, c.goal, xe, c.t, c.T, c.G, c.active, tm);
+    EvalOut e = eval_any<EV_GRAD>(c.pipe, rb, c.P, c.S, c.goal, xe, c.t, c.T, c.G, c.active, tm);
     ++evg;
     const float Je = grp_sum(e.cost, c.G);
     if (phase == PH_INIT) {
@@ -723,7 +784,8 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
         float xk[NJ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j) xk[j] = x[j] + al * d[j];
-        EvalOut ek = evaluate<EV_COST>(rb, c.P, c.S, c.goal, xk, c.t, c.T, c.G, c.active, tm);
+        EvalOut ek = eval_any<EV_COST>(c.pipe, rb, c.P, c.S, c.goal, xk, c.t, c.T, c.G, c.active,
+                                       tm);
         ++evc;
         float Jk = grp_sum(ek.cost, c.G);
         if (need && Jk <= J + c.P.c1 * al * gtd) chosen = kk;
@@ -926,7 +988,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   for (int j = 0; j < NJ; ++j) x[j] = active ? X[((size_t)seed * T + t) * NJ + j] : 0.f;
   float J;
   if (with_grad) {
-    EvalOut e = evaluate<EV_GRAD>(rb, P, Sm, goal, x, t, T, G, active, tm);
+    EvalOut e = eval_any<EV_GRAD>(use_pipe(rb, tm, G), rb, P, Sm, goal, x, t, T, G, active, tm);
     J = grp_sum(e.cost, G);
     float w = dJ ? dJ[seed] : 1.f;
     if (active && owner) {
@@ -934,7 +996,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
       for (int j = 0; j < NJ; ++j) dX[((size_t)seed * T + t) * NJ + j] = w * e.g[j];
     }
   } else {
-    EvalOut e = evaluate<EV_COST>(rb, P, Sm, goal, x, t, T, G, active, tm);
+    EvalOut e = eval_any<EV_COST>(use_pipe(rb, tm, G), rb, P, Sm, goal, x, t, T, G, active, tm);
     J = grp_sum(e.cost, G);
   }
   if (J_out && lane == 0) J_out[seed] = J;

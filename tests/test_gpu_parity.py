@@ -90,10 +90,12 @@ def test_sphere_centres(key):
         assert np.abs(c[s] - ref).max() < 1e-5
 
 
-@pytest.mark.parametrize("key", ["A", "B"])
-def test_cost_grad_random_trajectories(key):
+@pytest.mark.parametrize("key,T", [("A", 32), ("B", 32), ("A", 16), ("A", 9)])
+def test_cost_grad_random_trajectories(key, T):
+    """(A, T <= 16): four lanes per waypoint hold at most one sphere per
+    link, which selects the all-gathers-in-flight evaluation form."""
     su = setup(key, 1)
-    X = random_trajs(2, 16, 32, su.prob.q_start)
+    X = random_trajs(2, 16, T, su.prob.q_start)
     check_cost_grad(su, X)
 
 
