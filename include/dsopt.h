@@ -173,6 +173,24 @@ int ds_esdf_upload(ds_plan* plan, int32_t scene_id, const float* vals, int nx, i
                    float voxel, const float origin[3], void* stream);
 int ds_esdf_release(ds_plan* plan, int32_t scene_id);
 
+/* Build a scene's distance field on the GPU from an occupancy grid (the
+ * step before the optimiser: the paper builds its ESDF from depth with a
+ * GPU mapping library, Sec. 4.4 / Sec. 5.1).  `occ` (device or host) holds
+ * nx*ny*nz bytes, x fastest, nonzero = occupied, voxel (i,j,k) centred at
+ * origin + (i,j,k)*voxel.  Signed Euclidean distance by definition: a free
+ * voxel stores voxel * (distance to the nearest occupied voxel centre), an
+ * occupied voxel -voxel * (distance to the nearest free voxel centre),
+ * computed exactly by three separable squared-distance passes.  A grid with
+ * no occupied (no free) voxel yields values >= 1e9 * voxel in magnitude.
+ * The field becomes scene `scene_id` exactly as with ds_esdf_upload;
+ * `out_vals` (device, nx*ny*nz floats, may be NULL) receives a copy of the
+ * signed distances.  Temporary space (4 * nx*ny*nz floats) comes from the
+ * arena.  Errors: DS_ERR_INVALID (dims < 2 or > 1024, voxel <= 0),
+ * DS_ERR_NOMEM. */
+int ds_esdf_from_occupancy(ds_plan* plan, int32_t scene_id, const uint8_t* occ, int nx, int ny,
+                           int nz, float voxel, const float origin[3], float* out_vals,
+                           void* stream);
+
 /* Optimise n problems for params.n_iters iterations (Sec. 4.4).  n == 1
  * is the plain one-problem launch; n > 1 runs every seed of every problem
  * in one persistent launch over a work table, longest work first.

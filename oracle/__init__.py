@@ -66,6 +66,9 @@ def lib():
                                    D, C.c_double, D]
         L.orc_results.argtypes = [C.c_void_p, C.c_void_p, D, D, D, D, C.c_int, C.c_int, D, I32,
                                   C.c_int]
+        L.orc_esdf_from_occupancy.restype = C.c_int
+        L.orc_esdf_from_occupancy.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double,
+                                              C.c_void_p, C.c_int64, D, C.c_int]
         L.orc_quat_to_R.argtypes = [D, D]
         L.orc_R_to_quat.argtypes = [D, D]
         _lib = L
@@ -303,3 +306,22 @@ def sphere_centres(robot_h: RobotH, X):
     out = np.zeros((T, robot_h.ns, 3))
     lib().orc_spheres(robot_h.h, xp, T, out.ctypes.data_as(D))
     return out
+
+
+def esdf_from_occupancy(occ, voxel, which=None, threads=8):
+    """Signed distance of an occupancy grid occ [nz, ny, nx] (bool/uint8) at
+    all voxels (returns [nz, ny, nx]) or at flat indices ``which``."""
+    occ = np.ascontiguousarray(occ, dtype=np.uint8)
+    nz, ny, nx = occ.shape
+    if which is None:
+        out = np.zeros(occ.size)
+        wp, n = None, 0
+    else:
+        which = np.ascontiguousarray(which, dtype=np.int64)
+        out = np.zeros(len(which))
+        wp, n = which.ctypes.data_as(C.c_void_p), len(which)
+    rc = lib().orc_esdf_from_occupancy(occ.ctypes.data_as(C.c_void_p), nx, ny, nz, float(voxel),
+                                       wp, n, out.ctypes.data_as(D), threads)
+    if rc != 0:
+        raise ValueError("occupancy grid needs at least one occupied and one free voxel")
+    return out.reshape(occ.shape) if which is None else out

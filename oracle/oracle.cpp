@@ -961,3 +961,34 @@ void orc_quat_to_R(const double* q, double* R) { quat_to_R(q, R); }
 void orc_R_to_quat(const double* R, double* q) { R_to_quat(R, q); }
 
 }  // extern "C"
+
+// ===================================================== ESDF construction ====
+// Signed Euclidean distance field of an occupancy grid, by its definition:
+// a free voxel holds voxel * (distance to the nearest occupied voxel
+// centre), an occupied voxel -voxel * (distance to the nearest free voxel
+// centre); distances between voxel centres in index units.  Brute force
+// over all voxels, for the indices listed in `which` (all when null).
+extern "C" int orc_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz, double voxel,
+                                       const int64_t* which, int64_t n_which, double* out,
+                                       int nthreads) {
+  const int64_t N = (int64_t)nx * ny * nz;
+  std::vector<int> occ_idx, free_idx;
+  for (int64_t i = 0; i < N; ++i) (occ[i] ? occ_idx : free_idx).push_back((int)i);
+  if (occ_idx.empty() || free_idx.empty()) return -1;
+  const int64_t M = which ? n_which : N;
+#pragma omp parallel for schedule(dynamic, 64) num_threads(nthreads > 0 ? nthreads : 1)
+  for (int64_t m = 0; m < M; ++m) {
+    int64_t v = which ? which[m] : m;
+    int x = (int)(v % nx), y = (int)((v / nx) % ny), z = (int)(v / ((int64_t)nx * ny));
+    const std::vector<int>& other = occ[v] ? free_idx : occ_idx;
+    double best = std::numeric_limits<double>::infinity();
+    for (int w : other) {
+      int wx = w % nx, wy = (w / nx) % ny, wz = w / (nx * ny);
+      double dx = x - wx, dy = y - wy, dz = z - wz;
+      best = std::min(best, dx * dx + dy * dy + dz * dz);
+    }
+    double d = voxel * std::sqrt(best);
+    out[m] = occ[v] ? -d : d;
+  }
+  return 0;
+}

@@ -439,6 +439,47 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
   return DS_OK;
 }
 
+int ds_esdf_from_occupancy(ds_plan* p, int32_t scene_id, const uint8_t* occ, int nx, int ny,
+                           int nz, float voxel, const float origin[3], float* out_vals,
+                           void* stream) {
+  if (!p || !occ || !origin) return fail(DS_ERR_INVALID, "NULL argument");
+  if (nx < 2 || ny < 2 || nz < 2 || nx > 1024 || ny > 1024 || nz > 1024)
+    return fail(DS_ERR_INVALID, "grid dims must be in [2, 1024]");
+  if (!(voxel > 0) || !std::isfinite(voxel) || !finite_all(origin, 3))
+    return fail(DS_ERR_INVALID, "voxel must be > 0 and origin finite");
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  poll_deferred(p, false);
+  const size_t n = (size_t)nx * ny * nz;
+  const size_t fb = n * sizeof(float);
+  size_t occ_off = SIZE_MAX, work_off = arena_alloc(p, 5 * fb);
+  if (work_off == SIZE_MAX) return fail(DS_ERR_NOMEM, "arena full (distance transform, %zu B)", 5 * fb);
+  const uint8_t* occ_dev = occ;
+  hipPointerAttribute_t attr;
+  bool on_device = false;
+  if (hipPointerGetAttributes(&attr, occ) == hipSuccess)
+    on_device = attr.type == hipMemoryTypeDevice || attr.type == hipMemoryTypeManaged;
+  (void)hipGetLastError();
+  if (!on_device) {
+    occ_off = arena_alloc(p, n);
+    if (occ_off == SIZE_MAX) {
+      p->arena.release(work_off);
+      return fail(DS_ERR_NOMEM, "arena full (occupancy staging)");
+    }
+    HIP_TRY(hipMemcpyAsync(p->arena.ptr(occ_off), occ, n, hipMemcpyHostToDevice, s));
+    occ_dev = p->arena.ptr(occ_off);
+  }
+  float* w = reinterpret_cast<float*>(p->arena.ptr(work_off));
+  float* dist = w + 4 * n;
+  HIP_TRY(launch_esdf_from_occupancy(occ_dev, nx, ny, nz, voxel, w, w + n, w + 2 * n, w + 3 * n,
+                                     dist, s));
+  if (out_vals) HIP_TRY(hipMemcpyAsync(out_vals, dist, fb, hipMemcpyDeviceToDevice, s));
+  int rc = ds_esdf_upload(p, scene_id, dist, nx, ny, nz, voxel, origin, stream);
+  if (int r2 = defer_free(p, work_off, s)) return r2;
+  if (occ_off != SIZE_MAX)
+    if (int r2 = defer_free(p, occ_off, s)) return r2;
+  return rc;
+}
+
 int ds_esdf_release(ds_plan* p, int32_t scene_id) {
   if (!p) return fail(DS_ERR_INVALID, "NULL plan");
   auto it = p->scenes.find(scene_id);

@@ -108,6 +108,9 @@ hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* p
 hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
                           hipStream_t s);
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
+hipError_t launch_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz, float voxel,
+                                      float* w0, float* w1, float* w2, float* w3, float* out,
+                                      hipStream_t s);
 hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                              const TileDev* tiles, const int* tile_list, int* counter,
                              int max_tiles, int grid_blocks, int max_iters, int waves,

@@ -26,6 +26,19 @@ namespace dsk {
 namespace {
 
 constexpr unsigned RSRC_DWORD3 = 0x00020000u;   // raw buffer, gfx9 family
+
+// Pointers read from tables are generic to the compiler; these casts state
+// that they address global memory, so accesses use global (not flat)
+// instructions.
+#define DS_GLOBAL __attribute__((address_space(1)))
+template <class T>
+__device__ __forceinline__ DS_GLOBAL T* glb(T* p) {
+  return (DS_GLOBAL T*)p;
+}
+template <class T>
+__device__ __forceinline__ const DS_GLOBAL T* glb(const T* p) {
+  return (const DS_GLOBAL T*)p;
+}
 #ifndef DSOPT_CH
 #define DSOPT_CH 2
 #endif
@@ -300,7 +313,8 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   // wavefronts split its spheres: copy index and stride
   const int L = WAVE / G;
   const int lane = threadIdx.x & (WAVE - 1);
-  const int cp = tm.w * L + lane / G;
+  const int u = lane / G;
+  const int cp = tm.w * L + u;
   const int LW = tm.W * L;
   EvalOut o;
 #pragma unroll
@@ -526,14 +540,14 @@ struct TileCtx {
   const ProbDev* pb;
   Sampler S;
   Goal goal;
-  float* st;
+  DS_GLOBAL float* st;
   int lane, G, t, T, seed;
   bool owner;    // first copy of the waypoint: writes outputs and traces
   bool pipe;     // all-gathers-in-flight evaluation form
   bool active;   // t < T
 };
 
-__device__ __forceinline__ float* col(float* st, int base, int j, int lane) {
+__device__ __forceinline__ DS_GLOBAL float* col(DS_GLOBAL float* st, int base, int j, int lane) {
   return st + base + j * WAVE + lane;
 }
 
@@ -624,11 +638,11 @@ __device__ __forceinline__ void trace_row(float* buf, const TileCtx& c, int k, c
   if (!buf || !c.owner || c.t >= c.T) return;
   size_t base = (((size_t)k * c.pb->S + c.seed) * c.T + c.t) * NJ;
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) buf[base + j] = v[j];
+  for (int j = 0; j < NJ; ++j) glb(buf)[base + j] = v[j];
 }
 __device__ __forceinline__ void trace_scalar(float* buf, const TileCtx& c, int k, float v) {
   if (!buf || !c.owner || c.t != 0) return;
-  buf[(size_t)k * c.pb->S + c.seed] = v;
+  glb(buf)[(size_t)k * c.pb->S + c.seed] = v;
 }
 
 // Final per-seed results and output trajectory.
@@ -652,11 +666,11 @@ __device__ void finalize(const TileCtx& c, const float* x, Team& tm) {
   }
   jm = grp_max(jm, c.G);
   if (c.owner && c.t < c.T) {
-    float* ft = c.pb->final_traj + ((size_t)c.seed * c.T + c.t) * NJ;
+    DS_GLOBAL float* ft = glb(c.pb->final_traj) + ((size_t)c.seed * c.T + c.t) * NJ;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) ft[j] = x[j];
     if (c.pb->out_traj) {
-      float* ot = c.pb->out_traj + ((size_t)c.seed * c.T + c.t) * NJ;
+      DS_GLOBAL float* ot = glb(c.pb->out_traj) + ((size_t)c.seed * c.T + c.t) * NJ;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) ot[j] = x[j];
     }
@@ -674,10 +688,16 @@ __device__ void finalize(const TileCtx& c, const float* x, Team& tm) {
     sr.within_limits = okf > 0.5f ? 1 : 0;
     sr.success = (sr.valid && sr.collision_free && sr.within_limits && perr < c.P.tol_pos &&
                   rerr < c.P.tol_rot) ? 1 : 0;
-    sr.n_evals_cost = reinterpret_cast<const int*>(c.st)[ST_EVC + c.lane];
-    sr.n_evals_grad = reinterpret_cast<const int*>(c.st)[ST_EVG + c.lane];
+    sr.n_evals_cost = ((const DS_GLOBAL int*)c.st)[ST_EVC + c.lane];
+    sr.n_evals_grad = ((const DS_GLOBAL int*)c.st)[ST_EVG + c.lane];
     sr.pad = 0;
-    c.pb->seed_res[c.seed] = sr;
+    // field by field: the implicit struct copy has no global-address form
+    DS_GLOBAL ds_seed_result* o = glb(c.pb->seed_res) + c.seed;
+    o->cost = sr.cost; o->clearance = sr.clearance; o->pos_err = sr.pos_err;
+    o->rot_err = sr.rot_err; o->max_jerk = sr.max_jerk;
+    o->collision_free = sr.collision_free; o->within_limits = sr.within_limits;
+    o->success = sr.success; o->valid = sr.valid; o->n_evals_cost = sr.n_evals_cost;
+    o->n_evals_grad = sr.n_evals_grad; o->pad = 0;
   }
 }
 
@@ -700,7 +720,7 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
   c.pb = probs + td.prob;
   c.S = make_sampler(c.pb->sc);
   c.goal = make_goal(*c.pb);
-  c.st = td.state;
+  c.st = glb(td.state);
   c.lane = threadIdx.x & (WAVE - 1);
   c.G = td.G;
   c.t = c.lane & (c.G - 1);
@@ -711,7 +731,7 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
   c.active = c.t < c.T;
   const bool writer = tm.w == 0;   // the team's first wavefront writes state
   const int n_iters = c.pb->n_iters;
-  int* sti = reinterpret_cast<int*>(c.st);
+  DS_GLOBAL int* sti = (DS_GLOBAL int*)c.st;
   const ProbDev& pb = *c.pb;
 
   float x[NJ], g[NJ], d[NJ], xe[NJ], gt[NJ];
@@ -721,7 +741,7 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
   int phase;
   if (iter == 0) {
     if (c.active) {
-      const float* sp = pb.seeds + ((size_t)c.seed * c.T + c.t) * NJ;
+      const DS_GLOBAL float* sp = glb(pb.seeds) + ((size_t)c.seed * c.T + c.t) * NJ;
 #pragma unroll
       for (int j = 0; j < NJ; ++j) xe[j] = (c.t == 0) ? pb.qs[j] : sp[j];
     } else {
@@ -1055,6 +1075,53 @@ __global__ void k_esdf_pack(const float* __restrict__ v, int nx, int ny, int nz,
   }
 }
 
+// ---------------------------------------------- ESDF from an occupancy grid --
+// Exact squared Euclidean distance transform by separable passes: after the
+// pass along x, y and z, f(v) = min over marked voxels w of |v - w|^2 (index
+// units).  Every value is an integer below 2^24 (or the "none" sentinel), so
+// float arithmetic is exact.
+constexpr float EDT_NONE = 1e20f;
+
+__global__ void k_edt_init(const uint8_t* __restrict__ occ, long long n, int target,
+                           float* __restrict__ f) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    f[i] = ((occ[i] != 0) == (target != 0)) ? 0.f : EDT_NONE;
+}
+
+// One pass along `axis` (0 = x, 1 = y, 2 = z): one workgroup per line, the
+// line staged in LDS, every element scans the whole line.
+__global__ void __launch_bounds__(256)
+k_edt_pass(const float* __restrict__ fin, float* __restrict__ fout, int nx, int ny, int nz,
+           int axis) {
+  extern __shared__ float line[];
+  const int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
+  const long long stride = axis == 0 ? 1 : (axis == 1 ? (long long)nx : (long long)nx * ny);
+  // the line's first element
+  long long l = blockIdx.x, base;
+  if (axis == 0) base = l * nx;
+  else if (axis == 1) base = (l / nx) * (long long)nx * ny + (l % nx);
+  else base = l;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) line[q] = fin[base + q * stride];
+  __syncthreads();
+  for (int pidx = threadIdx.x; pidx < n; pidx += blockDim.x) {
+    float best = EDT_NONE;
+    for (int q = 0; q < n; ++q) {
+      float dq = (float)(pidx - q);
+      best = fminf(best, dq * dq + line[q]);
+    }
+    fout[base + pidx * stride] = best;
+  }
+}
+
+__global__ void k_edt_final(const uint8_t* __restrict__ occ, const float* __restrict__ d_occ,
+                            const float* __restrict__ d_free, long long n, float voxel,
+                            float* __restrict__ out) {
+  for (long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x; i < n;
+       i += (long long)gridDim.x * blockDim.x)
+    out[i] = occ[i] ? -voxel * sqrtf(d_free[i]) : voxel * sqrtf(d_occ[i]);
+}
+
 __global__ void k_zero_i32(int* p, int n) {
   int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = 0;
@@ -1120,6 +1187,33 @@ hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, floa
                           hipStream_t s) {
   int n = S * T;
   hipLaunchKernelGGL(k_spheres, dim3((n + 255) / 256), dim3(256), 0, s, rb, X, n, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz, float voxel,
+                                      float* w0, float* w1, float* w2, float* w3, float* out,
+                                      hipStream_t s) {
+  const long long n = (long long)nx * ny * nz;
+  const int blocks = (int)std::min<long long>((n + 255) / 256, 65536);
+  float* chain[2][2] = {{w0, w1}, {w2, w3}};
+  for (int c = 0; c < 2; ++c) {   // c = 0: distance to occupied, 1: to free
+    hipLaunchKernelGGL(k_edt_init, dim3(blocks), dim3(256), 0, s, occ, n, c == 0 ? 1 : 0,
+                       chain[c][0]);
+    float* a = chain[c][0];
+    float* b = chain[c][1];
+    for (int axis = 0; axis < 3; ++axis) {
+      int len = axis == 0 ? nx : (axis == 1 ? ny : nz);
+      long long lines = n / len;
+      hipLaunchKernelGGL(k_edt_pass, dim3((unsigned)lines), dim3(256), len * sizeof(float), s, a,
+                         b, nx, ny, nz, axis);
+      float* t = a;
+      a = b;
+      b = t;
+    }
+    chain[c][0] = a;   // result of the three passes
+  }
+  hipLaunchKernelGGL(k_edt_final, dim3(blocks), dim3(256), 0, s, occ, chain[0][0], chain[1][0],
+                     n, voxel, out);
   return hipGetLastError();
 }
 

@@ -28,7 +28,7 @@ MAX_SPHERES = 128
 
 EXPORTED = [
     "ds_version", "ds_last_error", "ds_plan_create", "ds_plan_destroy", "ds_esdf_upload",
-    "ds_esdf_release", "ds_optimize_seeds", "ds_optimize_traced", "ds_get_best",
+    "ds_esdf_release", "ds_esdf_from_occupancy", "ds_optimize_seeds", "ds_optimize_traced", "ds_get_best",
     "ds_get_seed_results", "ds_problem_release", "ds_cost", "ds_cost_grad",
     "ds_sphere_centres", "ds_serve_start", "ds_serve_submit", "ds_serve_step", "ds_serve_poll",
     "ds_serve_stats", "ds_serve_stop", "ds_kernel_timing", "ds_kernel_timing_read",
@@ -110,6 +110,8 @@ def load():
     L.ds_esdf_upload.argtypes = [vp, i32, vp, C.c_int, C.c_int, C.c_int, C.c_float,
                                  C.POINTER(C.c_float), vp]
     L.ds_esdf_release.argtypes = [vp, i32]
+    L.ds_esdf_from_occupancy.argtypes = [vp, i32, vp, C.c_int, C.c_int, C.c_int, C.c_float,
+                                         C.POINTER(C.c_float), vp, vp]
     L.ds_optimize_seeds.argtypes = [vp, C.POINTER(Problem), C.c_int, vp]
     L.ds_optimize_traced.argtypes = [vp, C.POINTER(Problem), f32p, f32p, f32p, f32p, f32p, vp]
     L.ds_get_best.argtypes = [vp, i32, vp, C.POINTER(Result)]
@@ -250,6 +252,23 @@ class Plan:
                                       nz, float(voxel), o, _stream(stream)))
         if src.device.type == "cuda":
             self._keep[("scene", scene_id)] = src
+
+    def scene_from_occupancy(self, scene_id, occ, voxel, origin, out=None, stream=None):
+        """occ: [nz, ny, nx] uint8/bool (numpy host array or torch tensor);
+        out: optional cuda float tensor [nz, ny, nx] receiving the signed
+        distances."""
+        import torch
+        if isinstance(occ, np.ndarray):
+            src = torch.from_numpy(np.ascontiguousarray(occ, dtype=np.uint8))
+        else:
+            src = occ.to(torch.uint8).contiguous()
+        nz, ny, nx = src.shape
+        o = (C.c_float * 3)(*[float(v) for v in origin])
+        check(self.lib.ds_esdf_from_occupancy(self.h, int(scene_id), C.c_void_p(src.data_ptr()),
+                                              nx, ny, nz, float(voxel), o, _ptr(out),
+                                              _stream(stream)))
+        if src.device.type == "cuda":
+            self._keep[("occ", scene_id)] = src
 
     def release_scene(self, scene_id):
         check(self.lib.ds_esdf_release(self.h, int(scene_id)))

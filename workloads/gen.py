@@ -298,6 +298,16 @@ def build_grids(scenes, threads: int = 8):
     return scenes
 
 
+def occupancy(scene: Scene) -> np.ndarray:
+    """Occupancy of the grid nodes (uint8 [nz, ny, nx]): 1 where the node
+    lies strictly inside a box.  Input for building the distance field on
+    the GPU."""
+    if scene.grid is not None:
+        return (scene.grid < 0).astype(np.uint8)
+    g = build_grid(scene)
+    return (g < 0).astype(np.uint8)
+
+
 def empty_scene(dims=(16, 16, 16), voxel=0.2, origin=(-1.6, -1.6, -1.6), value=1.0) -> Scene:
     sc = Scene(np.zeros((0, 3)), np.zeros((0, 3)), tuple(dims), f32(voxel),
                np.asarray(origin, dtype=np.float32))
