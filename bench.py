@@ -178,6 +178,15 @@ def run_batched(args, dsopt, torch, configs, params):
         for i in range(len(specs)):
             plan.release(base + i)
 
+    # evaluation counts of every seed (deterministic): algorithmic gather bytes
+    base = tagc[0]
+    tagc[0] += len(specs)
+    plan.optimize([dict(s, tag=base + i) for i, s in enumerate(specs)])
+    gbytes = 0.0
+    for i, p in enumerate(probs):
+        r = plan.seed_results(base + i, p.S)
+        gbytes += float(np.sum(evals_per_seed(r))) * p.T * robot.n_spheres * 32.0
+        plan.release(base + i)
     out = {}
     for name, fn in [("batched", batched), ("plain", plain)]:
         fn()
@@ -199,6 +208,11 @@ def run_batched(args, dsopt, torch, configs, params):
         log(f"[bench] batched-uneven {name}: {dt * 1e3:.2f} ms/batch, "
             f"{sw * N / dt:.3e} seed-waypoint evals/s")
     plan.close()
+    kb = out["batched"]["kernel_ms_per_launch"] / 1e3
+    out["roofline"] = {"bound": "hbm", "kernel": "k_optimize (one persistent launch)",
+                       "achieved": gbytes / kb / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                       "frac": gbytes / kb / 1e9 / HBM_PEAK_GBS,
+                       "algorithmic_bytes_per_launch": gbytes}
     out["speedup_batched_vs_plain"] = out["plain"]["ms_per_batch"] / out["batched"]["ms_per_batch"]
     out["workload"] = (f"batched-uneven: {len(probs)} problems, seeds U{{4..128}}, horizons "
                        f"U{{16..64}}, {sw} seed-waypoints, 128^3 ESDF per problem, {N} iters")
@@ -303,6 +317,26 @@ def run_serving(args, dsopt, torch, configs, params):
             "served": served, "plain_serial": plain}
 
 
+def run_esdf_build(args, dsopt, torch, configs, params, scene):
+    """Distance field of the cluttered scene built on the GPU from its
+    occupancy grid (exact signed EDT), timed with events."""
+    from workloads import gen
+    occ = torch.from_numpy(gen.occupancy(scene)).cuda()
+    plan = dsopt.Plan(configs.robot("B"), params.DEFAULT, 1, 1 << 30)
+    plan.scene_from_occupancy(0, occ, scene.voxel, scene.origin)
+    torch.cuda.synchronize()
+    reps = 5
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        plan.scene_from_occupancy(0, occ, scene.voxel, scene.origin)
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / reps
+    plan.close()
+    log(f"[bench] distance field from occupancy {scene.dims}: {ms:.2f} ms")
+    return {"grid": list(scene.dims), "ms": ms,
+            "what": "signed EDT of the occupancy grid + packing into gather records"}
+
+
 def cpu_baseline(single, params, configs):
     """The FP64 oracle on the same problem, all host threads, ~10 s."""
     import oracle
@@ -400,6 +434,8 @@ def main():
                      "algorithmic_bytes_per_launch": single["gather_bytes"],
                      "evals_per_seed": single["evals_per_seed"]},
     }
+    rec["esdf_from_occupancy"] = run_esdf_build(args, dsopt, torch, configs, params,
+                                                single["scene"])
     if not args.no_batched:
         rec["batched"] = run_batched(args, dsopt, torch, configs, params)
     if not args.no_serving:

@@ -18,7 +18,9 @@
  *     two copies of q_0 before and two of q_{T-1} after (rest at both ends);
  *   - C_goal: w_pos |p_ee - p_d|^2 + w_rot (3 - tr(R_d^T R_ee)) / 4 at the
  *     last waypoint;
- *   - joint limits: w_limit * squared excess outside [q_lo, q_hi].
+ *   - joint limits: w_limit * squared excess outside [q_lo, q_hi];
+ *   - optional C_self: w_self * hinge of (|c_a - c_b| - r_a - r_b) over
+ *     sphere pairs on links at least two apart.
  * The optimiser is L-BFGS (two-loop recursion) with a backtracking search
  * over step sizes 1, 1/2, ..., 2^-(n_ls-1) (largest step meeting the Armijo
  * condition, else the cheapest candidate below the current cost, else no
@@ -104,6 +106,10 @@ typedef struct ds_params {
                              parallelism per seed for latency-bound launches (few
                              seeds); results depend on it only through the
                              order of floating-point sums */
+  float w_self;        /* self-collision weight (App. A.6 C_self): hinge on the
+                          separation of every sphere pair on links at least two
+                          apart; 0 switches the term off.  When on, the reported
+                          clearance and collision-free flag include these pairs. */
 } ds_params;
 
 /* One planning problem (Sec. 3).  `seeds` are the seed trajectories

@@ -89,7 +89,7 @@ def _nullable(a):
     return None if a is None else a.ctypes.data_as(D)
 
 
-TERMS = ["world", "vel", "acc", "jerk", "goal_pos", "goal_rot", "limit"]
+TERMS = ["world", "vel", "acc", "jerk", "goal_pos", "goal_rot", "limit", "self"]
 RESULT_FIELDS = ["J", "clearance", "pos_err", "rot_err", "max_jerk", "collision_free",
                  "within_limits", "success", "valid"]
 
@@ -167,7 +167,7 @@ class Oracle:
         J = np.zeros(S)
         G = np.zeros((S, T, 7)) if grad else None
         A = np.zeros((S, T, 7)) if absg else None
-        TM = np.zeros((S, 7)) if terms else None
+        TM = np.zeros((S, len(TERMS))) if terms else None
         lib().orc_cost(self.robot.h, self.grid.h, self._pp, qsp, gp, xp, S, T,
                        J.ctypes.data_as(D), _nullable(G), _nullable(A), _nullable(TM),
                        self.threads)

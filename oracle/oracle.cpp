@@ -62,6 +62,7 @@ struct Params {
   double wc, eps, lv, la, lj, wp, wr, wl;
   int m, nls;
   double c1, delta0, dmax, dt, tol_pos, tol_rot;
+  double ws;   // self-collision weight (0: the term is off)
 };
 
 struct Problem {
@@ -246,7 +247,8 @@ double hinge_d(double D, double eps) {
 }
 
 // ------------------------------------------------------------------- cost --
-enum { TERM_WORLD, TERM_VEL, TERM_ACC, TERM_JERK, TERM_GOALP, TERM_GOALR, TERM_LIMIT, NTERMS };
+enum { TERM_WORLD, TERM_VEL, TERM_ACC, TERM_JERK, TERM_GOALP, TERM_GOALR, TERM_LIMIT, TERM_SELF,
+       NTERMS };
 
 // Padded sequence P_k = q_{clamp(k-2, 0, T-1)}, k = 0 .. T+3.
 inline int pidx(int k, int T) { return std::min(std::max(k - 2, 0), T - 1); }
@@ -285,6 +287,45 @@ double cost(const Robot& rb, const Grid& G, const Params& P, const Problem& pr,
           if (Aout) absg[(size_t)t * NJ + i] += std::fabs(v);
         }
       }
+    }
+  }
+  // -- self-collision (App. A.6 C_self): every pair of spheres on links at
+  // least two apart, the same hinge on their separation
+  //    D_ab = |c_a - c_b| - r_a - r_b,
+  // force w_s phi'(D) n on a and its opposite on b (n = unit c_a - c_b).
+  if (P.ws != 0.0) {
+    std::vector<double> cen((size_t)rb.ns * 3);
+    for (int t = 0; t < T; ++t) {
+      fk(rb, X + (size_t)t * NJ, Tf);
+      for (int s = 0; s < rb.ns; ++s) apply(Tf[rb.link[s] - 1], &rb.off[3 * s], &cen[3 * s]);
+      for (int a = 0; a < rb.ns; ++a)
+        for (int b = 0; b < rb.ns; ++b) {
+          if (rb.link[b] - rb.link[a] < 2) continue;
+          const double* ca = &cen[3 * a];
+          const double* cb = &cen[3 * b];
+          double dv[3] = {ca[0] - cb[0], ca[1] - cb[1], ca[2] - cb[2]};
+          double dist = std::sqrt(dot3(dv, dv));
+          double D = dist - rb.rad[a] - rb.rad[b];
+          tm[TERM_SELF] += P.ws * hinge(D, P.eps);
+          if (!(Gout || Aout)) continue;
+          double dphi = P.ws * hinge_d(D, P.eps);
+          if (dphi == 0.0 || dist == 0.0) continue;
+          double f[3] = {dphi * dv[0] / dist, dphi * dv[1] / dist, dphi * dv[2] / dist};
+          for (int side = 0; side < 2; ++side) {
+            const double* c = side ? cb : ca;
+            int l = side ? rb.link[b] : rb.link[a];
+            double sg = side ? -1.0 : 1.0;
+            for (int i = 0; i < l; ++i) {
+              double zi[3] = {Tf[i].R[2], Tf[i].R[5], Tf[i].R[8]};
+              double r[3] = {c[0] - Tf[i].p[0], c[1] - Tf[i].p[1], c[2] - Tf[i].p[2]};
+              double jc[3];
+              cross(zi, r, jc);
+              double v = sg * dot3(f, jc);
+              if (Gout) grad[(size_t)t * NJ + i] += v;
+              if (Aout) absg[(size_t)t * NJ + i] += std::fabs(v);
+            }
+          }
+        }
     }
   }
   // -- smoothness on the padded sequence
@@ -602,6 +643,22 @@ SeedResult results(const Robot& rb, const Grid& G, const Params& P, const Proble
       clr = std::min(clr, sample(G, c).d - rb.rad[s]);
     }
   }
+  if (P.ws != 0.0) {
+    // with the self-collision term on, the clearance also covers sphere
+    // pairs on links at least two apart
+    std::vector<double> cen((size_t)rb.ns * 3);
+    for (int t = 0; t < T; ++t) {
+      fk(rb, X + (size_t)t * NJ, Tf);
+      for (int s = 0; s < rb.ns; ++s) apply(Tf[rb.link[s] - 1], &rb.off[3 * s], &cen[3 * s]);
+      for (int a = 0; a < rb.ns; ++a)
+        for (int b = 0; b < rb.ns; ++b) {
+          if (rb.link[b] - rb.link[a] < 2) continue;
+          double dv[3] = {cen[3 * a] - cen[3 * b], cen[3 * a + 1] - cen[3 * b + 1],
+                          cen[3 * a + 2] - cen[3 * b + 2]};
+          clr = std::min(clr, std::sqrt(dot3(dv, dv)) - rb.rad[a] - rb.rad[b]);
+        }
+    }
+  }
   R.clearance = clr;
   R.collision_free = clr > 0 ? 1 : 0;
   fk(rb, X + (size_t)(T - 1) * NJ, Tf);
@@ -653,6 +710,7 @@ Params make_params(const double* p) {
   P.m = (int)p[8]; P.nls = (int)p[9];
   P.c1 = p[10]; P.delta0 = p[11]; P.dmax = p[12]; P.dt = p[13];
   P.tol_pos = p[14]; P.tol_rot = p[15];
+  P.ws = p[16];
   return P;
 }
 

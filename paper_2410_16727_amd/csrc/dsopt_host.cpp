@@ -313,7 +313,7 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
     if (!finite_all(sp.offset, 3) || !(sp.radius >= 0) || !std::isfinite(sp.radius))
       return fail(DS_ERR_INVALID, "sphere %d: bad offset/radius", s);
   }
-  if (!(prm->eps > 0) || prm->history < 1 || prm->history > DS_MAX_HISTORY || prm->n_ls < 1 ||
+  if (!std::isfinite(prm->w_self) || !(prm->eps > 0) || prm->history < 1 || prm->history > DS_MAX_HISTORY || prm->n_ls < 1 ||
       prm->n_ls > DS_MAX_LS || prm->n_iters < 0 || prm->block_iters < 1 || !(prm->dt > 0) ||
       !(prm->delta0 > 0) || !(prm->step_max > 0) ||
       !(prm->waves_per_seed == 1 || prm->waves_per_seed == 2 || prm->waves_per_seed == 4 ||
@@ -353,6 +353,7 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   }
   ParamsDev& P = p->params;
   P.wc = prm->w_collision;
+  P.ws = prm->w_self;
   P.eps = prm->eps;
   P.inv_eps = 1.f / prm->eps;
   P.half_inv_eps = 0.5f / prm->eps;

@@ -26,7 +26,7 @@ struct RobotDev {
 };
 
 struct ParamsDev {
-  float wc, eps, inv_eps, half_inv_eps;
+  float wc, ws, eps, inv_eps, half_inv_eps;
   float lv, la, lj, wp, wr, wl;
   float c1, delta0, dmax, dt, tol_pos, tol_rot;
   int32_t m, nls, n_iters, block_iters;

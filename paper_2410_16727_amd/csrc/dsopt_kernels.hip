@@ -19,6 +19,7 @@
 
 #include <cfloat>
 #include <cmath>
+#include <type_traits>
 
 #include "dsopt_internal.h"
 
@@ -297,6 +298,106 @@ __device__ __forceinline__ void project(const Twists& tw, int l, const float* FM
   }
 }
 
+// Self-collision share of this lane (App. A.6 C_self): every pair of spheres
+// on links at least two apart, hinge on D = |c_a - c_b| - r_a - r_b; the
+// pairs of each link pair are split over the W*L copies.  The sweep keeps
+// the seven link frames; forces go into per-link wrenches that are projected
+// on the joint axes at the end.
+template <int MODE>
+__device__ __attribute__((noinline)) void self_collision(const RobotDev* __restrict__ rb,
+                                                         const ParamsDev& P, const float* q,
+                                                         int cp, int LW, float& selfsum,
+                                                         float& clr, float* g) {
+  constexpr bool GRAD = (MODE == EV_GRAD);
+  float Rf[NJ][9], pf[NJ][3];
+  float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
+  float p[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int l = 0; l < NJ; ++l) {
+    const float* F = rb->F[l];
+    float A[9], pa[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        A[3 * r + c] = R[3 * r] * F[c] + R[3 * r + 1] * F[4 + c] + R[3 * r + 2] * F[8 + c];
+      pa[r] = R[3 * r] * F[3] + R[3 * r + 1] * F[7] + R[3 * r + 2] * F[11] + p[r];
+    }
+    float sn, cs;
+    sincosf(q[l], &sn, &cs);
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+      float a0 = A[3 * r], a1 = A[3 * r + 1];
+      R[3 * r] = cs * a0 + sn * a1;
+      R[3 * r + 1] = cs * a1 - sn * a0;
+      R[3 * r + 2] = A[3 * r + 2];
+      p[r] = pa[r];
+    }
+#pragma unroll
+    for (int k = 0; k < 9; ++k) Rf[l][k] = R[k];
+    pf[l][0] = p[0]; pf[l][1] = p[1]; pf[l][2] = p[2];
+  }
+  float FM[NJ][6];
+#pragma unroll
+  for (int l = 0; l < NJ; ++l)
+#pragma unroll
+    for (int k = 0; k < 6; ++k) FM[l][k] = 0.f;
+#pragma unroll
+  for (int la = 0; la < NJ; ++la) {
+#pragma unroll
+    for (int lb = la + 2; lb < NJ; ++lb) {
+      const int a0 = rb->link_begin[la], na = rb->link_begin[la + 1] - a0;
+      const int b0 = rb->link_begin[lb], nb = rb->link_begin[lb + 1] - b0;
+      for (int k = cp; k < na * nb; k += LW) {
+        const int ia = k / nb, ib = k - ia * nb;
+        const float4 sa = rb->sph[a0 + ia], sb = rb->sph[b0 + ib];
+        float ca[3], cb[3];
+#pragma unroll
+        for (int r = 0; r < 3; ++r) {
+          ca[r] = Rf[la][3 * r] * sa.x + Rf[la][3 * r + 1] * sa.y + Rf[la][3 * r + 2] * sa.z + pf[la][r];
+          cb[r] = Rf[lb][3 * r] * sb.x + Rf[lb][3 * r + 1] * sb.y + Rf[lb][3 * r + 2] * sb.z + pf[lb][r];
+        }
+        float dx = ca[0] - cb[0], dy = ca[1] - cb[1], dz = ca[2] - cb[2];
+        float dist = sqrtf(dx * dx + dy * dy + dz * dz);
+        float D = dist - sa.w - sb.w;
+        float De = D - P.eps;
+        float phi = (D < P.eps) ? De * De * P.half_inv_eps : 0.f;
+        phi = (D < 0.f) ? 0.5f * P.eps - D : phi;
+        selfsum += phi;
+        if (MODE == EV_RESULT) clr = fminf(clr, D);
+        if (GRAD) {
+          float dphi = (D < P.eps) ? De * P.inv_eps : 0.f;
+          dphi = (D < 0.f) ? -1.f : dphi;
+          float w = (dist > 0.f) ? P.ws * dphi / dist : 0.f;
+          float fx = w * dx, fy = w * dy, fz = w * dz;
+          FM[la][0] += fx; FM[la][1] += fy; FM[la][2] += fz;
+          FM[la][3] += ca[1] * fz - ca[2] * fy;
+          FM[la][4] += ca[2] * fx - ca[0] * fz;
+          FM[la][5] += ca[0] * fy - ca[1] * fx;
+          FM[lb][0] -= fx; FM[lb][1] -= fy; FM[lb][2] -= fz;
+          FM[lb][3] -= cb[1] * fz - cb[2] * fy;
+          FM[lb][4] -= cb[2] * fx - cb[0] * fz;
+          FM[lb][5] -= cb[0] * fy - cb[1] * fx;
+        }
+      }
+    }
+  }
+  if (GRAD) {
+#pragma unroll
+    for (int l = 0; l < NJ; ++l) {
+#pragma unroll
+      for (int i = 0; i <= l; ++i) {
+        const float zi[3] = {Rf[i][2], Rf[i][5], Rf[i][8]};
+        const float* oi = pf[i];
+        float tx = FM[l][3] - (oi[1] * FM[l][2] - oi[2] * FM[l][1]);
+        float ty = FM[l][4] - (oi[2] * FM[l][0] - oi[0] * FM[l][2]);
+        float tz = FM[l][5] - (oi[0] * FM[l][1] - oi[1] * FM[l][0]);
+        g[i] += zi[0] * tx + zi[1] * ty + zi[2] * tz;
+      }
+    }
+  }
+}
+
 // One evaluation of the objective at this lane's configuration q.
 // PIPE (every lane holds at most one sphere of each link, W*L >= spheres
 // per link): the forward sweep issues each link's record load as soon as
@@ -408,8 +509,17 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       if (GRAD) project(tw, l, FM, o.g);
     }
   }
-  // sum the sphere shares of the L lanes of this waypoint (butterfly: every
-  // copy ends with the same value)
+  // collision cost share: world hinge sum, plus the self-collision pairs
+  // when that term is on
+  float coll = P.wc * phisum;
+  if (P.ws != 0.f) {
+    float selfsum = 0.f;
+    self_collision<MODE>(rb, P, q, cp, LW, selfsum, clr, o.g);
+    coll += P.ws * selfsum;
+  }
+  phisum = coll;
+  // sum the shares of the L lanes of this waypoint (butterfly: every copy
+  // ends with the same value)
   for (int off = G; off < WAVE; off <<= 1) {
     phisum += __shfl_xor(phisum, off);
     if (MODE == EV_RESULT) clr = fminf(clr, __shfl_xor(clr, off));
@@ -508,7 +618,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     if (GRAD) o.g[j] += 2.f * P.wl * (hp - lp);
   }
   float sm = smoothness<GRAD>(P, q, t, T, o.g);
-  float c = P.wc * phisum + P.wl * lim + sm + (last ? goal_cost : 0.f);
+  float c = phisum + P.wl * lim + sm + (last ? goal_cost : 0.f);
   o.cost = active ? c : 0.f;
   if (GRAD) {
 #pragma unroll
@@ -551,11 +661,42 @@ __device__ __forceinline__ DS_GLOBAL float* col(DS_GLOBAL float* st, int base, i
   return st + base + j * WAVE + lane;
 }
 
-// L-BFGS direction (two-loop recursion over the ring in the tile state),
+// History ring (rho, y^T y, s, y per slot) of one seed, laid out like the
+// tile state's history section: in the tile state (global) for single
+// wavefronts, or in LDS for a team for the duration of a launch.
+constexpr int H_RHO = 0, H_YY = H_RHO + DS_MAX_HISTORY * WAVE, H_S = H_YY + DS_MAX_HISTORY * WAVE,
+              H_Y = H_S + DS_MAX_HISTORY * NJ * WAVE, H_FLOATS = H_Y + DS_MAX_HISTORY * NJ * WAVE;
+static_assert(ST_YY - ST_RHO == H_YY && ST_S - ST_RHO == H_S && ST_Y - ST_RHO == H_Y &&
+                  ST_FLOATS - ST_RHO == H_FLOATS,
+              "history layout must match the tile state");
+
+template <class Ptr>
+struct Hist {
+  Ptr h;      // base of the history section
+  int lane;
+  __device__ __forceinline__ float s(int k, int j) const { return h[H_S + (k * NJ + j) * WAVE + lane]; }
+  __device__ __forceinline__ float y(int k, int j) const { return h[H_Y + (k * NJ + j) * WAVE + lane]; }
+  __device__ __forceinline__ float rho(int k) const { return h[H_RHO + k * WAVE + lane]; }
+  __device__ __forceinline__ float yy(int k) const { return h[H_YY + k * WAVE + lane]; }
+  __device__ __forceinline__ void push(int k, const float* sv, const float* yv, float r, float q) const {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      h[H_S + (k * NJ + j) * WAVE + lane] = sv[j];
+      h[H_Y + (k * NJ + j) * WAVE + lane] = yv[j];
+    }
+    h[H_RHO + k * WAVE + lane] = r;
+    h[H_YY + k * WAVE + lane] = q;
+  }
+};
+using GHist = Hist<DS_GLOBAL float*>;
+using LHist = Hist<float*>;
+
+// L-BFGS direction (two-loop recursion over the history ring),
 // steepest-descent restart and infinity-norm cap.  cnt/head are this
 // lane's group's history count and ring head.
-__device__ __forceinline__ void direction(const TileCtx& c, const float* g, int& cnt, int head,
-                                          float* d) {
+template <class H>
+__device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const float* g, int& cnt,
+                                          int head, float* d) {
   const int m = c.P.m;
   float gmax = 0.f;
 #pragma unroll
@@ -580,10 +721,10 @@ __device__ __forceinline__ void direction(const TileCtx& c, const float* g, int&
       float s[NJ], y[NJ];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        s[j] = *col(c.st, ST_S + slot * NJ * WAVE, j, c.lane);
-        y[j] = *col(c.st, ST_Y + slot * NJ * WAVE, j, c.lane);
+        s[j] = hist.s(slot, j);
+        y[j] = hist.y(slot, j);
       }
-      float rho = c.st[ST_RHO + slot * WAVE + c.lane];
+      float rho = hist.rho(slot);
       float dt = grp_sum(dot7(s, q), c.G);
       bool use = k < cnt;
       float ak = rho * dt;
@@ -593,8 +734,8 @@ __device__ __forceinline__ void direction(const TileCtx& c, const float* g, int&
     }
   }
   int newest = (head - 1 + m) % m;
-  float rho_n = c.st[ST_RHO + newest * WAVE + c.lane];
-  float yy_n = c.st[ST_YY + newest * WAVE + c.lane];
+  float rho_n = hist.rho(newest);
+  float yy_n = hist.yy(newest);
   float gamma = 1.f / (rho_n * yy_n);   // s^T y / y^T y
 #pragma unroll
   for (int j = 0; j < NJ; ++j) q[j] *= gamma;
@@ -605,10 +746,10 @@ __device__ __forceinline__ void direction(const TileCtx& c, const float* g, int&
       float s[NJ], y[NJ];
 #pragma unroll
       for (int j = 0; j < NJ; ++j) {
-        s[j] = *col(c.st, ST_S + slot * NJ * WAVE, j, c.lane);
-        y[j] = *col(c.st, ST_Y + slot * NJ * WAVE, j, c.lane);
+        s[j] = hist.s(slot, j);
+        y[j] = hist.y(slot, j);
       }
-      float rho = c.st[ST_RHO + slot * WAVE + c.lane];
+      float rho = hist.rho(slot);
       float b = rho * grp_sum(dot7(y, q), c.G);
       bool use = k < cnt;
 #pragma unroll
@@ -711,9 +852,10 @@ enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
 //          cost-only candidates while a seed of the tile has no Armijo step;
 //          if a seed accepted alpha < 1, evaluate there (ACCEPT), else update;
 //   ACCEPT take the accepted point's cost and gradient, update.
-__device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
+template <bool LDS_HIST>
+__device__ __attribute__((noinline)) void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
                          const ProbDev* __restrict__ probs, const TileDev& td, int max_iters,
-                         Team& tm) {
+                         Team& tm, float* hist_lds) {
   TileCtx c;
   c.rb = rb;
   c.P = *pp;
@@ -764,6 +906,19 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
     phase = PH_DIR;
   }
   int n_left = min(max_iters, n_iters - iter);
+  // the history ring: LDS copy for a team, else the tile state
+  typename std::conditional<LDS_HIST, LHist, GHist>::type hist;
+  hist.lane = c.lane;
+  if constexpr (LDS_HIST) {
+    hist.h = hist_lds;
+    if (iter > 0 && n_left > 0) {   // resume: bring the ring into LDS
+      const DS_GLOBAL float* src = c.st + ST_RHO;
+      for (int i = threadIdx.x; i < H_FLOATS; i += tm.W * WAVE) hist_lds[i] = src[i];
+    }
+    tm.sync();
+  } else {
+    hist.h = c.st + ST_RHO;
+  }
 
   for (;;) {
     if (phase == PH_DIR) {
@@ -771,7 +926,7 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
       trace_row(pb.tr_x, c, iter, x);
       trace_row(pb.tr_g, c, iter, g);
       trace_scalar(pb.tr_J, c, iter, J);
-      direction(c, g, cnt, head, d);
+      direction(c, hist, g, cnt, head, d);
       trace_row(pb.tr_d, c, iter, d);
       gtd = grp_sum(dot7(g, d), c.G);
 #pragma unroll
@@ -845,15 +1000,7 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
     float yy = grp_sum(dot7(y, y), c.G);
     if (accept) {
       if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy)) {
-        if (writer) {
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) {
-            *col(c.st, ST_S + head * NJ * WAVE, j, c.lane) = s[j];
-            *col(c.st, ST_Y + head * NJ * WAVE, j, c.lane) = y[j];
-          }
-          c.st[ST_RHO + head * WAVE + c.lane] = 1.f / sy;
-          c.st[ST_YY + head * WAVE + c.lane] = yy;
-        }
+        if (writer) hist.push(head, s, y, 1.f / sy, yy);
         head = (head + 1) % c.P.m;
         cnt = min(cnt + 1, c.P.m);
       }
@@ -868,7 +1015,13 @@ __device__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __res
     phase = PH_DIR;
     tm.sync();   // the writer's history is visible to the team
   }
-  // persist the state
+  // persist the state (a team writes its LDS ring back for a later launch)
+  if constexpr (LDS_HIST) {
+    if (iter < n_iters) {
+      DS_GLOBAL float* dst = c.st + ST_RHO;
+      for (int i = threadIdx.x; i < H_FLOATS; i += tm.W * WAVE) dst[i] = hist_lds[i];
+    }
+  }
   if (writer) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
@@ -926,7 +1079,12 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
     if (mine >= nt) break;
     const int ti = tile_list ? tile_list[mine] : mine;
     TileDev td = tiles[ti];
-    run_tile(rb, pp, probs, td, max_iters, tm);
+    if (tm.W > 1) {
+      run_tile<true>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE);
+      __syncthreads();   // the LDS ring is free for the next tile
+    } else {
+      run_tile<false>(rb, pp, probs, td, max_iters, tm, nullptr);
+    }
   }
 }
 
@@ -1138,7 +1296,9 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
 }
 
 int team_block(int W) { return (W > 1 ? W : WAVES_PER_BLOCK) * WAVE; }
-size_t team_lds(int W) { return W > 1 ? (size_t)2 * W * PART * WAVE * sizeof(float) : 0; }
+size_t team_lds(int W) {
+  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS) * sizeof(float) : 0;
+}
 
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,

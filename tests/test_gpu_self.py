@@ -1,0 +1,73 @@
+"""GPU parity of the optional self-collision term (C_self of App. A.6)
+against the FP64 oracle: cost/gradient on trajectories with self-contact,
+a lockstep optimisation, and flags including self-clearance."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+if not torch.cuda.is_available():
+    pytest.skip("needs a GPU", allow_module_level=True)
+
+import oracle  # noqa: E402
+from paper_2410_16727_amd import dsopt  # noqa: E402
+from workloads import configs, gen, params  # noqa: E402
+
+from test_gpu_parity import AMB_TOL, COST_RTOL, GRAD_RTOL, lockstep_check  # noqa: E402
+
+PS = dict(params.DEFAULT, w_self=50.0)
+
+
+def fat(key):
+    rb = configs.robot(key)
+    return gen.Robot(rb.link_lengths, rb.frames, rb.q_lo, rb.q_hi, rb.sphere_link,
+                     rb.sphere_offset, (rb.sphere_radius * 1.6).astype(np.float32))
+
+
+class SelfSetup:
+    def __init__(self, key, iters, waves):
+        self.key = key
+        self.robot = fat(key)
+        self.scene = configs.scenes(key, only={0})[0]
+        self.prob = configs.problems(key)[0]
+        self.iters = iters
+        self.plan = dsopt.Plan(self.robot, dict(PS, waves_per_seed=waves), iters, 512 << 20)
+        self.plan.upload_scene(0, self.scene.grid, self.scene.voxel, self.scene.origin)
+        self.O = oracle.Oracle(self.robot, self.scene, params.as_list(PS), threads=8)
+
+
+@pytest.mark.parametrize("key,T", [("B", 32), ("A", 16), ("B", 64)])
+def test_self_cost_grad_parity(key, T):
+    su = SelfSetup(key, 1, 1)
+    X = gen.random_trajectories(np.random.default_rng(T), 8, T, su.prob.q_start)
+    ref = su.O.cost(su.prob.q_start, su.prob.goal, X.astype(np.float64), grad=True, absg=True,
+                    terms=True)
+    assert np.all(ref["terms"][:, 7] > 0)
+    J, G = su.plan.cost_grad(0, su.prob.q_start, su.prob.goal, torch.from_numpy(X).cuda())
+    J, G = J.cpu().numpy(), G.cpu().numpy()
+    assert (np.abs(J - ref["J"]) / ref["J"]).max() < COST_RTOL
+    for s in range(X.shape[0]):
+        amb, _ = su.O.ambiguity(X[s].astype(np.float64), AMB_TOL)
+        scale = max(np.abs(ref["G"][s]).max(), np.abs(ref["A"][s]).max())
+        assert (np.abs(G[s] - ref["G"][s]) - amb).max() <= GRAD_RTOL * scale
+    su.plan.close()
+
+
+@pytest.mark.parametrize("waves", [1, 8])
+def test_self_lockstep_and_flags(waves):
+    su = SelfSetup("A", 15, waves)
+    seeds = configs.seeds_for("A", 0, su.prob)
+    sd = torch.from_numpy(seeds).cuda()
+    tr = su.plan.optimize_traced({"scene": 0, "q_start": su.prob.q_start, "goal": su.prob.goal,
+                                  "seeds": sd, "tag": 3})
+    torch.cuda.synchronize()
+    tr = {k: v.double().cpu().numpy() for k, v in tr.items()}
+    lockstep_check(su, tr, seeds.shape[0])
+    res = su.plan.seed_results(3, seeds.shape[0])
+    ref = su.O.results(su.prob.q_start, su.prob.goal, tr["x"][-1])
+    amb = np.abs(ref["clearance"]) < 1e-5
+    for f in ["collision_free", "success", "valid"]:
+        assert ((res[f] == ref[f].astype(int)) | amb).all(), f
+    assert np.abs(res["clearance"] - ref["clearance"]).max() < 1e-4
+    su.plan.close()
