@@ -238,6 +238,17 @@ int ds_cost(ds_plan* plan, const ds_problem* prob, const float* X, int S, int T,
 int ds_cost_grad(ds_plan* plan, const ds_problem* prob, const float* X, int S, int T,
                  const float* dJ, float* J_out, float* dX, void* stream);
 
+/* Cost-gradient guidance for seed sampling (the appendix on cost-guided
+ * diffusion sampling, Eq. 4: the denoiser mean is moved along the cost
+ * gradient, n gradient steps per denoising step).  Runs n_steps steps
+ * X <- X - alpha * dJ/dX of the objective for the scene/goal of `prob` on S
+ * trajectories X (device [S][T][7], updated in place; row 0 stays fixed)
+ * in one launch; J_out (device [S], may be NULL) receives the cost after the
+ * last step.  Reading: a descent step (the printed sign would ascend the
+ * cost).  Errors as ds_cost_grad; n_steps >= 0. */
+int ds_guide(ds_plan* plan, const ds_problem* prob, float* X, int S, int T, float alpha,
+             int n_steps, float* J_out, void* stream);
+
 /* Sphere centres of X (device [S][T][7]) into out (device
  * [S][T][n_spheres][3]), in the robot's sphere order (parity checks). */
 int ds_sphere_centres(ds_plan* plan, const float* X, int S, int T, float* out, void* stream);

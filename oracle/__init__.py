@@ -69,6 +69,8 @@ def lib():
         L.orc_esdf_from_occupancy.restype = C.c_int
         L.orc_esdf_from_occupancy.argtypes = [C.c_void_p, C.c_int, C.c_int, C.c_int, C.c_double,
                                               C.c_void_p, C.c_int64, D, C.c_int]
+        L.orc_guide.argtypes = [C.c_void_p, C.c_void_p, D, D, D, D, C.c_int, C.c_int, C.c_double,
+                                C.c_int, C.c_int]
         L.orc_quat_to_R.argtypes = [D, D]
         L.orc_R_to_quat.argtypes = [D, D]
         _lib = L
@@ -225,6 +227,16 @@ class Oracle:
         lib().orc_lockstep(self.robot.h, self.grid.h, self._pp, qsp, gp, T, iters, xp, gsp, jp,
                            dp, ap, amb_tol, rep.ctypes.data_as(D))
         return rep
+
+    def guide(self, qs, goal, X, alpha, n):
+        """n steps X <- X - alpha * grad J (returns the new X)."""
+        X = np.array(X, dtype=np.float64, copy=True)
+        S, T, _ = X.shape
+        qs, qsp = _d(qs)
+        goal, gp = _d(goal)
+        lib().orc_guide(self.robot.h, self.grid.h, self._pp, qsp, gp, X.ctypes.data_as(D), S, T,
+                        float(alpha), int(n), self.threads)
+        return X
 
     def results(self, qs, goal, X):
         X, xp = _d(X)

@@ -1014,6 +1014,25 @@ void orc_results(void* rb, void* g, const double* params, const double* qs, cons
   best[1] = any;
 }
 
+// Guidance steps X <- X - alpha * grad J (rows 1..T-1), n times, per seed.
+void orc_guide(void* rb, void* g, const double* params, const double* qs, const double* goal,
+               double* X, int S, int T, double alpha, int n, int nthreads) {
+  Params P = make_params(params);
+  Problem pr = make_problem(qs, goal);
+  const Robot& R = *static_cast<Robot*>(rb);
+  const Grid& G = *static_cast<Grid*>(g);
+  size_t stride = (size_t)T * NJ;
+#pragma omp parallel for schedule(dynamic) num_threads(nthreads > 0 ? nthreads : 1)
+  for (int s = 0; s < S; ++s) {
+    std::vector<double> gr(stride);
+    double* x = X + s * stride;
+    for (int k = 0; k < n; ++k) {
+      cost(R, G, P, pr, x, T, gr.data(), nullptr, nullptr);
+      for (size_t e = 0; e < stride; ++e) x[e] -= alpha * gr[e];
+    }
+  }
+}
+
 // Helpers for the quaternion pins.
 void orc_quat_to_R(const double* q, double* R) { quat_to_R(q, R); }
 void orc_R_to_quat(const double* R, double* q) { R_to_quat(R, q); }

@@ -568,6 +568,25 @@ int ds_cost_grad(ds_plan* p, const ds_problem* prob, const float* X, int S, int 
   return cost_common(p, prob, X, S, T, dJ, J_out, dX, 1, stream);
 }
 
+int ds_guide(ds_plan* p, const ds_problem* prob, float* X, int S, int T, float alpha, int n_steps,
+             float* J_out, void* stream) {
+  if (!p || !prob || !X) return fail(DS_ERR_INVALID, "NULL argument");
+  if (S < 1 || T < DS_MIN_T || T > DS_MAX_T) return fail(DS_ERR_INVALID, "bad S/T (%d, %d)", S, T);
+  if (n_steps < 0 || !std::isfinite(alpha)) return fail(DS_ERR_INVALID, "bad alpha / n_steps");
+  if (int rc = validate_problem(p, *prob, false)) return rc;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  poll_deferred(p, false);
+  size_t off = arena_alloc(p, sizeof(ProbDev));
+  if (off == SIZE_MAX) return fail(DS_ERR_NOMEM, "arena full");
+  ProbDev pd = make_probdev(p, *prob);
+  pd.S = S;
+  pd.T = T;
+  ProbDev* dev = reinterpret_cast<ProbDev*>(p->arena.ptr(off));
+  if (int rc = upload(p, dev, &pd, sizeof pd, s)) return rc;
+  HIP_TRY(launch_guide(p->robot_dev, p->params_dev, dev, X, S, T, alpha, n_steps, J_out, s));
+  return defer_free(p, off, s);
+}
+
 int ds_kernel_timing(ds_plan* p, int enable) {
   if (!p) return fail(DS_ERR_INVALID, "NULL plan");
   p->timing = enable != 0;

@@ -1180,6 +1180,46 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   if (J_out && lane == 0) J_out[seed] = J;
 }
 
+// Guidance: n gradient steps x <- x - alpha * g on every trajectory, one
+// wavefront per seed (same evaluation as the optimiser).
+__global__ void __launch_bounds__(BLOCK)
+k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
+        const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
+        int n_steps, float* __restrict__ J_out) {
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+  if (seed >= S) return;   // whole wavefront past the end
+  const int t = lane & (G - 1);
+  const bool owner = lane < G;
+  const bool active = t < T;
+  ParamsDev P = *pp;
+  Sampler Sm = make_sampler(pb->sc);
+  Goal goal = make_goal(*pb);
+  Team tm;
+  tm.W = 1;
+  tm.w = 0;
+  tm.lds = nullptr;
+  tm.buf = 0;
+  const bool pipe = use_pipe(rb, tm, G);
+  float x[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) x[j] = active ? X[((size_t)seed * T + t) * NJ + j] : 0.f;
+  for (int k = 0; k < n_steps; ++k) {
+    EvalOut e = eval_any<EV_GRAD>(pipe, rb, P, Sm, goal, x, t, T, G, active, tm);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) x[j] -= alpha * e.g[j];
+  }
+  if (J_out) {
+    EvalOut e = eval_any<EV_COST>(pipe, rb, P, Sm, goal, x, t, T, G, active, tm);
+    float J = grp_sum(e.cost, G);
+    if (lane == 0) J_out[seed] = J;
+  }
+  if (active && owner) {
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) X[((size_t)seed * T + t) * NJ + j] = x[j];
+  }
+}
+
 // Sphere centres (parity dump), one thread per seed-waypoint.
 __global__ void k_spheres(const RobotDev* __restrict__ rb, const float* __restrict__ X, int n,
                           float* __restrict__ out) {
@@ -1340,6 +1380,15 @@ hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* p
   int blocks = (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
   hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, dJ,
                      J_out, dX, with_grad);
+  return hipGetLastError();
+}
+
+hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob, float* X,
+                        int S, int T, float alpha, int n_steps, float* J_out, hipStream_t s) {
+  int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
+  int blocks = (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  hipLaunchKernelGGL(k_guide, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, alpha,
+                     n_steps, J_out);
   return hipGetLastError();
 }
 

@@ -30,7 +30,7 @@ EXPORTED = [
     "ds_version", "ds_last_error", "ds_plan_create", "ds_plan_destroy", "ds_esdf_upload",
     "ds_esdf_release", "ds_esdf_from_occupancy", "ds_optimize_seeds", "ds_optimize_traced", "ds_get_best",
     "ds_get_seed_results", "ds_problem_release", "ds_cost", "ds_cost_grad",
-    "ds_sphere_centres", "ds_serve_start", "ds_serve_submit", "ds_serve_step", "ds_serve_poll",
+    "ds_sphere_centres", "ds_guide", "ds_serve_start", "ds_serve_submit", "ds_serve_step", "ds_serve_poll",
     "ds_serve_stats", "ds_serve_stop", "ds_kernel_timing", "ds_kernel_timing_read",
 ]
 
@@ -121,6 +121,8 @@ def load():
     L.ds_cost_grad.argtypes = [vp, C.POINTER(Problem), f32p, C.c_int, C.c_int, f32p, f32p, f32p,
                                vp]
     L.ds_sphere_centres.argtypes = [vp, f32p, C.c_int, C.c_int, f32p, vp]
+    L.ds_guide.argtypes = [vp, C.POINTER(Problem), f32p, C.c_int, C.c_int, C.c_float, C.c_int,
+                           f32p, vp]
     L.ds_kernel_timing.argtypes = [vp, C.c_int]
     L.ds_kernel_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
     L.ds_serve_start.argtypes = [vp, C.c_int, C.c_int, vp]
@@ -337,6 +339,16 @@ class Plan:
         check(self.lib.ds_cost_grad(self.h, C.byref(pr), _ptr(X), S, T, _ptr(dJ), _ptr(J),
                                     _ptr(dX), _stream(stream)))
         return J, dX
+
+    def guide(self, scene, q_start, goal, X, alpha, n_steps, stream=None):
+        """In place: n_steps steps X <- X - alpha * dJ/dX; returns J after."""
+        import torch
+        S, T, _ = X.shape
+        J = torch.empty(S, dtype=torch.float32, device=X.device)
+        pr = problem_struct(scene, q_start, goal)
+        check(self.lib.ds_guide(self.h, C.byref(pr), _ptr(X), S, T, float(alpha), int(n_steps),
+                                _ptr(J), _stream(stream)))
+        return J
 
     def sphere_centres(self, X, stream=None):
         import torch

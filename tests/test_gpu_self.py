@@ -71,3 +71,34 @@ def test_self_lockstep_and_flags(waves):
         assert ((res[f] == ref[f].astype(int)) | amb).all(), f
     assert np.abs(res["clearance"] - ref["clearance"]).max() < 1e-4
     su.plan.close()
+
+
+def test_guidance_matches_oracle():
+    """Cost-gradient guidance (a few descent steps in one launch) against the
+    oracle's steps from the same trajectories."""
+    key = "B"
+    robot = configs.robot(key)
+    scene = configs.scenes(key, only={0})[0]
+    prob = configs.problems(key)[0]
+    plan = dsopt.Plan(robot, params.DEFAULT, 1, 512 << 20)
+    plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
+    X = gen.random_trajectories(np.random.default_rng(8), 16, 32, prob.q_start)
+    Xd = torch.from_numpy(X).cuda()
+    alpha, n = 2e-5, 4
+    J = plan.guide(0, prob.q_start, prob.goal, Xd, alpha, n).cpu().numpy()
+    O = oracle.Oracle(robot, scene, params.as_list(), threads=8)
+    ref = O.guide(prob.q_start, prob.goal, X.astype(np.float64), alpha, n)
+    Xg = Xd.cpu().numpy().astype(np.float64)
+    # per step the update differs by alpha * (gradient tolerance)
+    g0 = O.cost(prob.q_start, prob.goal, X.astype(np.float64), grad=True, absg=True)
+    scale = max(np.abs(g0["G"]).max(), np.abs(g0["A"]).max())
+    # (a sample crossing a trilinear cell face may take the neighbouring
+    # cell's gradient in float32: allow a few elements a larger difference)
+    err = np.abs(Xg - ref)
+    tol = n * alpha * 1e-3 * scale + 1e-6
+    assert np.quantile(err, 0.99) <= tol
+    assert err.max() <= 100 * tol
+    Jref = O.cost(prob.q_start, prob.goal, ref)["J"]
+    assert (np.abs(J - Jref) / Jref).max() < 1e-3
+    assert np.all(Jref < g0["J"])
+    plan.close()

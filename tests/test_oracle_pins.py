@@ -454,3 +454,16 @@ def test_best_seed_rule_and_invalid_seeds(robot):
     res = O.results(prob.q_start, prob.goal, X)
     assert res["valid"].tolist() == [1, 0, 1, 1]
     assert res["best"] == 0          # equal costs: lowest index wins
+
+
+def test_guidance_step_is_gradient_descent(robot, sceneB, probB):
+    """One guidance step equals x - alpha * grad (the oracle's gradient is
+    pinned by central differences above); small steps decrease the cost."""
+    O = make_oracle(robot, sceneB)
+    X = gen.random_trajectories(np.random.default_rng(21), 3, 8, probB.q_start).astype(np.float64)
+    c = O.cost(probB.q_start, probB.goal, X, grad=True)
+    X1 = O.guide(probB.q_start, probB.goal, X, 1e-6, 1)
+    assert np.abs(X1 - (X - 1e-6 * c["G"])).max() < 1e-15
+    J1 = O.cost(probB.q_start, probB.goal, X1)["J"]
+    assert np.all(J1 < c["J"])
+    assert np.array_equal(X1[:, 0], X[:, 0])
