@@ -110,6 +110,11 @@ typedef struct ds_params {
                           separation of every sphere pair on links at least two
                           apart; 0 switches the term off.  When on, the reported
                           clearance and collision-free flag include these pairs. */
+  int32_t swept_samples; /* 0..8 configurations per segment, linearly interpolated
+                            between consecutive waypoints (the paper's trajectories
+                            are interpolated linearly), add to C_world and to the
+                            clearance; their gradient splits (1 - tau, tau) onto
+                            the two waypoints.  0: waypoints only. */
 } ds_params;
 
 /* One planning problem (Sec. 3).  `seeds` are the seed trajectories

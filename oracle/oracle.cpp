@@ -63,6 +63,7 @@ struct Params {
   int m, nls;
   double c1, delta0, dmax, dt, tol_pos, tol_rot;
   double ws;   // self-collision weight (0: the term is off)
+  int nsub;    // swept sub-samples per segment (0: waypoints only)
 };
 
 struct Problem {
@@ -289,6 +290,47 @@ double cost(const Robot& rb, const Grid& G, const Params& P, const Problem& pr,
       }
     }
   }
+  // -- swept collision: nsub configurations q = (1 - tau) q_t + tau q_{t+1},
+  // tau = i / (nsub + 1), on every segment between waypoints (the paper's
+  // trajectories are linearly interpolated between waypoints); the
+  // gradient at q splits (1 - tau, tau) onto the two waypoints
+  if (P.nsub > 0) {
+    double qi[NJ];
+    for (int t = 0; t + 1 < T; ++t)
+      for (int i = 1; i <= P.nsub; ++i) {
+        double tau = (double)i / (P.nsub + 1);
+        for (int j = 0; j < NJ; ++j)
+          qi[j] = (1.0 - tau) * X[(size_t)t * NJ + j] + tau * X[(size_t)(t + 1) * NJ + j];
+        fk(rb, qi, Tf);
+        for (int s = 0; s < rb.ns; ++s) {
+          int l = rb.link[s];
+          double c[3];
+          apply(Tf[l - 1], &rb.off[3 * s], c);
+          Sample Sm = sample(G, c);
+          double D = Sm.d - rb.rad[s];
+          tm[TERM_WORLD] += P.wc * hinge(D, P.eps);
+          if (!(Gout || Aout)) continue;
+          double dphi = P.wc * hinge_d(D, P.eps);
+          if (dphi == 0.0) continue;
+          double f[3] = {dphi * Sm.g[0], dphi * Sm.g[1], dphi * Sm.g[2]};
+          for (int k = 0; k < l; ++k) {
+            double zk[3] = {Tf[k].R[2], Tf[k].R[5], Tf[k].R[8]};
+            double r[3] = {c[0] - Tf[k].p[0], c[1] - Tf[k].p[1], c[2] - Tf[k].p[2]};
+            double jc[3];
+            cross(zk, r, jc);
+            double v = dot3(f, jc);
+            if (Gout) {
+              grad[(size_t)t * NJ + k] += (1.0 - tau) * v;
+              grad[(size_t)(t + 1) * NJ + k] += tau * v;
+            }
+            if (Aout) {
+              absg[(size_t)t * NJ + k] += std::fabs((1.0 - tau) * v);
+              absg[(size_t)(t + 1) * NJ + k] += std::fabs(tau * v);
+            }
+          }
+        }
+      }
+  }
   // -- self-collision (App. A.6 C_self): every pair of spheres on links at
   // least two apart, the same hinge on their separation
   //    D_ab = |c_a - c_b| - r_a - r_b,
@@ -420,49 +462,73 @@ double cost(const Robot& rb, const Grid& G, const Params& P, const Problem& pr,
 // Per-element bound on how far the gradient can move when an FP32 caller
 // picks the neighbouring trilinear cell for a sample within ``tol`` voxel of
 // a cell face: |grad d(cell) - grad d(neighbour)| * |w_c phi'| * |J_c|.
+// One configuration q; the bound goes into row[0..6].
+static int ambiguity_config(const Robot& rb, const Grid& G, const Params& P, const double* q,
+                            double tol, double* row) {
+  int cnt = 0;
+  Frame Tf[8];
+  int n[3] = {G.nx, G.ny, G.nz};
+  fk(rb, q, Tf);
+  for (int s = 0; s < rb.ns; ++s) {
+    int l = rb.link[s];
+    double c[3];
+    apply(Tf[l - 1], &rb.off[3 * s], c);
+    Sample S = sample(G, c);
+    double D = S.d - rb.rad[s];
+    double dphi = std::fabs(P.wc * hinge_d(D, P.eps));
+    double worst = 0;
+    for (int a = 0; a < 3; ++a) {
+      double u = (c[a] - G.o[a]) / G.h;
+      double near_lo = std::fabs(u - std::floor(u));
+      double near_hi = std::fabs(std::ceil(u) - u);
+      bool near_face = std::min(near_lo, near_hi) < tol;
+      bool near_clamp = std::fabs(u) < tol || std::fabs(u - (n[a] - 1)) < tol;
+      if (!near_face && !near_clamp) continue;
+      for (int sgn = -1; sgn <= 1; sgn += 2) {
+        int cell[3] = {S.cell[0], S.cell[1], S.cell[2]};
+        cell[a] += sgn;
+        if (cell[a] < 0 || cell[a] > n[a] - 2) continue;
+        Sample A = sample_in_cell(G, c, cell);
+        for (int b = 0; b < 3; ++b) worst = std::max(worst, std::fabs(A.g[b] - S.g[b]));
+      }
+      if (near_clamp) worst = std::max(worst, std::fabs(S.graw[a]));
+    }
+    if (worst == 0 || dphi == 0) continue;
+    ++cnt;
+    for (int i = 0; i < l; ++i) {
+      double zi[3] = {Tf[i].R[2], Tf[i].R[5], Tf[i].R[8]};
+      double r[3] = {c[0] - Tf[i].p[0], c[1] - Tf[i].p[1], c[2] - Tf[i].p[2]};
+      double jc[3];
+      cross(zi, r, jc);
+      row[i] += dphi * worst * std::sqrt(3.0) * std::sqrt(dot3(jc, jc));
+    }
+  }
+  return cnt;
+}
+
+// The bound for every waypoint of X[T][7] and, with swept sub-samples, for
+// every interpolated configuration, spread onto the segment's two
+// waypoints with the weights its gradient takes (1 - tau, tau).  Row 0 (the
+// pinned start) stays zero.
 void ambiguity(const Robot& rb, const Grid& G, const Params& P, const double* X, int T,
                double tol, double* amb, int* n_amb) {
   std::fill(amb, amb + (size_t)T * NJ, 0.0);
   int cnt = 0;
-  Frame Tf[8];
-  int n[3] = {G.nx, G.ny, G.nz};
-  for (int t = 1; t < T; ++t) {
-    fk(rb, X + (size_t)t * NJ, Tf);
-    for (int s = 0; s < rb.ns; ++s) {
-      int l = rb.link[s];
-      double c[3];
-      apply(Tf[l - 1], &rb.off[3 * s], c);
-      Sample S = sample(G, c);
-      double D = S.d - rb.rad[s];
-      double dphi = std::fabs(P.wc * hinge_d(D, P.eps));
-      double worst = 0;
-      for (int a = 0; a < 3; ++a) {
-        double u = (c[a] - G.o[a]) / G.h;
-        double near_lo = std::fabs(u - std::floor(u));
-        double near_hi = std::fabs(std::ceil(u) - u);
-        bool near_face = std::min(near_lo, near_hi) < tol;
-        bool near_clamp = std::fabs(u) < tol || std::fabs(u - (n[a] - 1)) < tol;
-        if (!near_face && !near_clamp) continue;
-        for (int sgn = -1; sgn <= 1; sgn += 2) {
-          int cell[3] = {S.cell[0], S.cell[1], S.cell[2]};
-          cell[a] += sgn;
-          if (cell[a] < 0 || cell[a] > n[a] - 2) continue;
-          Sample A = sample_in_cell(G, c, cell);
-          for (int b = 0; b < 3; ++b) worst = std::max(worst, std::fabs(A.g[b] - S.g[b]));
-        }
-        if (near_clamp) worst = std::max(worst, std::fabs(S.graw[a]));
-      }
-      if (worst == 0 || dphi == 0) continue;
-      ++cnt;
-      for (int i = 0; i < l; ++i) {
-        double zi[3] = {Tf[i].R[2], Tf[i].R[5], Tf[i].R[8]};
-        double r[3] = {c[0] - Tf[i].p[0], c[1] - Tf[i].p[1], c[2] - Tf[i].p[2]};
-        double jc[3];
-        cross(zi, r, jc);
-        amb[(size_t)t * NJ + i] += dphi * worst * std::sqrt(3.0) * std::sqrt(dot3(jc, jc));
+  for (int t = 1; t < T; ++t) cnt += ambiguity_config(rb, G, P, X + (size_t)t * NJ, tol,
+                                                      amb + (size_t)t * NJ);
+  for (int t = 0; t + 1 < T; ++t)
+    for (int i = 1; i <= P.nsub; ++i) {
+      double tau = (double)i / (P.nsub + 1);
+      double qi[NJ], row[NJ] = {0, 0, 0, 0, 0, 0, 0};
+      for (int j = 0; j < NJ; ++j)
+        qi[j] = X[(size_t)t * NJ + j] + tau * (X[(size_t)(t + 1) * NJ + j] - X[(size_t)t * NJ + j]);
+      cnt += ambiguity_config(rb, G, P, qi, tol, row);
+      for (int j = 0; j < NJ; ++j) {
+        amb[(size_t)t * NJ + j] += (1 - tau) * row[j];
+        amb[(size_t)(t + 1) * NJ + j] += tau * row[j];
       }
     }
-  }
+  for (int j = 0; j < NJ; ++j) amb[j] = 0.0;
   if (n_amb) *n_amb = cnt;
 }
 
@@ -643,6 +709,21 @@ SeedResult results(const Robot& rb, const Grid& G, const Params& P, const Proble
       clr = std::min(clr, sample(G, c).d - rb.rad[s]);
     }
   }
+  if (P.nsub > 0) {
+    double qi[NJ];
+    for (int t = 0; t + 1 < T; ++t)
+      for (int i = 1; i <= P.nsub; ++i) {
+        double tau = (double)i / (P.nsub + 1);
+        for (int j = 0; j < NJ; ++j)
+          qi[j] = (1.0 - tau) * X[(size_t)t * NJ + j] + tau * X[(size_t)(t + 1) * NJ + j];
+        fk(rb, qi, Tf);
+        for (int s = 0; s < rb.ns; ++s) {
+          double c[3];
+          apply(Tf[rb.link[s] - 1], &rb.off[3 * s], c);
+          clr = std::min(clr, sample(G, c).d - rb.rad[s]);
+        }
+      }
+  }
   if (P.ws != 0.0) {
     // with the self-collision term on, the clearance also covers sphere
     // pairs on links at least two apart
@@ -711,6 +792,7 @@ Params make_params(const double* p) {
   P.c1 = p[10]; P.delta0 = p[11]; P.dmax = p[12]; P.dt = p[13];
   P.tol_pos = p[14]; P.tol_rot = p[15];
   P.ws = p[16];
+  P.nsub = (int)p[17];
   return P;
 }
 

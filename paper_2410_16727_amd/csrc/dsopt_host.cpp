@@ -269,7 +269,7 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   blocks = std::max(1, std::min(blocks, p->cu_count * p->blocks_per_cu));
   if (int rc = timed_launch(p, s, [&]() {
         return launch_optimize(p->robot_dev, p->params_dev, pd_dev, td_dev, total_tiles, counter,
-                               blocks, p->params.n_iters, W, s);
+                               blocks, p->params.n_iters, W, params_ext(p->params), s);
       }))
     return rc;
   HIP_TRY(launch_best(pd_dev, n, nullptr, s));
@@ -313,7 +313,8 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
     if (!finite_all(sp.offset, 3) || !(sp.radius >= 0) || !std::isfinite(sp.radius))
       return fail(DS_ERR_INVALID, "sphere %d: bad offset/radius", s);
   }
-  if (!std::isfinite(prm->w_self) || !(prm->eps > 0) || prm->history < 1 || prm->history > DS_MAX_HISTORY || prm->n_ls < 1 ||
+  if (!std::isfinite(prm->w_self) || prm->swept_samples < 0 || prm->swept_samples > 8 ||
+      !(prm->eps > 0) || prm->history < 1 || prm->history > DS_MAX_HISTORY || prm->n_ls < 1 ||
       prm->n_ls > DS_MAX_LS || prm->n_iters < 0 || prm->block_iters < 1 || !(prm->dt > 0) ||
       !(prm->delta0 > 0) || !(prm->step_max > 0) ||
       !(prm->waves_per_seed == 1 || prm->waves_per_seed == 2 || prm->waves_per_seed == 4 ||
@@ -325,7 +326,6 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   hipDeviceProp_t prop;
   HIP_TRY(hipGetDeviceProperties(&prop, p->device));
   p->cu_count = prop.multiProcessorCount;
-  p->blocks_per_cu = optimize_blocks_per_cu(prm->waves_per_seed);
   p->arena.init(static_cast<uint8_t*>(arena_dev), arena_bytes);
 
   RobotDev& rb = p->robot;
@@ -363,6 +363,8 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   P.tol_pos = prm->tol_pos; P.tol_rot = prm->tol_rot;
   P.m = prm->history; P.nls = prm->n_ls; P.n_iters = prm->n_iters; P.block_iters = prm->block_iters;
   P.waves = prm->waves_per_seed;
+  P.nsub = prm->swept_samples;
+  p->blocks_per_cu = optimize_blocks_per_cu(P.waves, params_ext(P));
 
   p->robot_off = p->arena.alloc(sizeof(RobotDev));
   p->params_off = p->arena.alloc(sizeof(ParamsDev));
@@ -554,7 +556,8 @@ static int cost_common(ds_plan* p, const ds_problem* prob, const float* X, int S
   pd.T = T;
   ProbDev* dev = reinterpret_cast<ProbDev*>(p->arena.ptr(off));
   if (int rc = upload(p, dev, &pd, sizeof pd, s)) return rc;
-  HIP_TRY(launch_cost(p->robot_dev, p->params_dev, dev, X, S, T, dJ, J_out, dX, with_grad, s));
+  HIP_TRY(launch_cost(p->robot_dev, p->params_dev, dev, X, S, T, dJ, J_out, dX, with_grad,
+                      params_ext(p->params), s));
   return defer_free(p, off, s);
 }
 
@@ -583,7 +586,8 @@ int ds_guide(ds_plan* p, const ds_problem* prob, float* X, int S, int T, float a
   pd.T = T;
   ProbDev* dev = reinterpret_cast<ProbDev*>(p->arena.ptr(off));
   if (int rc = upload(p, dev, &pd, sizeof pd, s)) return rc;
-  HIP_TRY(launch_guide(p->robot_dev, p->params_dev, dev, X, S, T, alpha, n_steps, J_out, s));
+  HIP_TRY(launch_guide(p->robot_dev, p->params_dev, dev, X, S, T, alpha, n_steps, J_out,
+                       params_ext(p->params), s));
   return defer_free(p, off, s);
 }
 

@@ -31,6 +31,7 @@ struct ParamsDev {
   float c1, delta0, dmax, dt, tol_pos, tol_rot;
   int32_t m, nls, n_iters, block_iters;
   int32_t waves;         // wavefronts per seed (1, 2, 4 or 8)
+  int32_t nsub;          // swept sub-samples per segment
 };
 
 // One resident scene: the 8 corners of cell (i,j,k) are the 32-byte record
@@ -94,19 +95,22 @@ struct SlotDev {
 // Releases the serving state of a plan (dsopt_serve.cpp).
 void ds_serve_free(ds_plan* plan);
 
-// Launch wrappers (dsopt_kernels.hip).
+// Launch wrappers (dsopt_kernels.hip).  `ext` selects the kernel variants
+// with the optional terms (self-collision, swept sub-samples) compiled in.
 namespace dsk {
+inline bool params_ext(const ParamsDev& P) { return P.ws != 0.f || P.nsub > 0; }
 hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* rec,
                             hipStream_t s);
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
-                           int max_iters, int waves, hipStream_t s);
+                           int max_iters, int waves, bool ext, hipStream_t s);
 hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s);
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
-                       int with_grad, hipStream_t s);
+                       int with_grad, bool ext, hipStream_t s);
 hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob, float* X,
-                        int S, int T, float alpha, int n_steps, float* J_out, hipStream_t s);
+                        int S, int T, float alpha, int n_steps, float* J_out, bool ext,
+                        hipStream_t s);
 hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
                           hipStream_t s);
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
@@ -115,8 +119,8 @@ hipError_t launch_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz
                                       hipStream_t s);
 hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                              const TileDev* tiles, const int* tile_list, int* counter,
-                             int max_tiles, int grid_blocks, int max_iters, int waves,
+                             int max_tiles, int grid_blocks, int max_iters, int waves, bool ext,
                              hipStream_t s);
 int team_block(int waves);
-int optimize_blocks_per_cu(int waves);
+int optimize_blocks_per_cu(int waves, bool ext);
 }  // namespace dsk

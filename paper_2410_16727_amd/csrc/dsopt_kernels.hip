@@ -398,32 +398,24 @@ __device__ __attribute__((noinline)) void self_collision(const RobotDev* __restr
   }
 }
 
-// One evaluation of the objective at this lane's configuration q.
+// The sweep over the chain for one configuration q: FK, this lane's share
+// of the sphere samples (hinge sum into phisum, min clearance into clr) and,
+// with GRAD, the link wrenches projected on the joint axes into g.  On
+// return R, p hold the frame of link 7 and tw the joint twists.
 // PIPE (every lane holds at most one sphere of each link, W*L >= spheres
-// per link): the forward sweep issues each link's record load as soon as
-// its frame exists and the samples are consumed after the sweep, so one
-// memory round trip covers the whole evaluation.  Otherwise each link is
-// processed in chunks of CH gathers right after its frame.
+// per link): the sweep issues each link's record load as soon as its frame
+// exists and consumes the samples afterwards, so one memory round trip
+// covers the whole configuration.  Otherwise each link is processed in
+// chunks of CH gathers right after its frame.
 template <int MODE, bool PIPE>
-__device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
-                                            const ParamsDev& P, const Sampler& S, const Goal& goal,
-                                            const float* q, int t, int T, int G, bool active,
-                                            Team& tm) {
+__device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const ParamsDev& P,
+                                      const Sampler& S, const float* q, int cp, int LW,
+                                      Twists& tw, float* R, float* p, float& phisum, float& clr,
+                                      float* g) {
   constexpr bool GRAD = (MODE == EV_GRAD);
-  // the L = 64/G lanes holding the same waypoint in each of the W
-  // wavefronts split its spheres: copy index and stride
-  const int L = WAVE / G;
-  const int lane = threadIdx.x & (WAVE - 1);
-  const int u = lane / G;
-  const int cp = tm.w * L + u;
-  const int LW = tm.W * L;
-  EvalOut o;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) o.g[j] = 0.f;
-  float R[9] = {1.f, 0.f, 0.f, 0.f, 1.f, 0.f, 0.f, 0.f, 1.f};
-  float p[3] = {0.f, 0.f, 0.f};
-  Twists tw;
-  float phisum = 0.f, clr = FLT_MAX;
+  R[0] = 1.f; R[1] = 0.f; R[2] = 0.f; R[3] = 0.f; R[4] = 1.f; R[5] = 0.f;
+  R[6] = 0.f; R[7] = 0.f; R[8] = 1.f;
+  p[0] = p[1] = p[2] = 0.f;
   // PIPE: the lane's sample of every link
   float4 pa_[PIPE ? NJ : 1], pz_[PIPE ? NJ : 1];
   float pc_[PIPE ? NJ : 1][3], pr_[PIPE ? NJ : 1];
@@ -495,7 +487,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
                             clr, FM);
       }
     }
-    if (GRAD) project(tw, l, FM, o.g);
+    if (GRAD) project(tw, l, FM, g);
   }
   if (PIPE) {
 #pragma unroll
@@ -506,13 +498,76 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
         sphere_term<MODE>(P, S, cl, pa_[l], pz_[l], pr_[l], pc_[l][0], pc_[l][1], pc_[l][2],
                           phisum, clr, FM);
       }
-      if (GRAD) project(tw, l, FM, o.g);
+      if (GRAD) project(tw, l, FM, g);
     }
   }
+}
+
+// One evaluation of the objective at this lane's configuration q (its
+// waypoint) and, with swept sub-samples, at the configurations interpolated
+// towards the next waypoint.
+template <int MODE, bool PIPE, bool EXT>
+__device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
+                                            const ParamsDev& P, const Sampler& S, const Goal& goal,
+                                            const float* q, int t, int T, int G, bool active,
+                                            Team& tm) {
+  constexpr bool GRAD = (MODE == EV_GRAD);
+  // the L = 64/G lanes holding the same waypoint in each of the W
+  // wavefronts split its spheres: copy index and stride
+  const int L = WAVE / G;
+  const int lane = threadIdx.x & (WAVE - 1);
+  const int cp = tm.w * L + lane / G;
+  const int LW = tm.W * L;
+  EvalOut o;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) o.g[j] = 0.f;
+  float phisum = 0.f, clr = FLT_MAX;
+  if (EXT && P.nsub > 0) {
+    // swept collision: q + tau (q_next - q), tau = i / (nsub + 1); the
+    // gradient splits (1 - tau) here and tau onto the next waypoint
+    float qn[NJ], gsh[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      qn[j] = __shfl_down(q[j], 1);
+      gsh[j] = 0.f;
+    }
+    const bool seg = active && t <= T - 2;
+    for (int i = 1; i <= P.nsub; ++i) {
+      const float tau = (float)i / (float)(P.nsub + 1);
+      float qi[NJ], gi[NJ], Rs[9], ps[3];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        qi[j] = q[j] + tau * (qn[j] - q[j]);
+        gi[j] = 0.f;
+      }
+      Twists tws;
+      float ph = 0.f, cl = FLT_MAX;
+      sweep<MODE, PIPE>(rb, P, S, qi, cp, LW, tws, Rs, ps, ph, cl, gi);
+      if (seg) {
+        phisum += ph;
+        clr = fminf(clr, cl);
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) {
+          o.g[j] += (1.f - tau) * gi[j];
+          gsh[j] += tau * gi[j];
+        }
+      }
+    }
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        float up = __shfl_up(gsh[j], 1);
+        o.g[j] += (t >= 1) ? up : 0.f;
+      }
+    }
+  }
+  float R[9], p[3];
+  Twists tw;
+  sweep<MODE, PIPE>(rb, P, S, q, cp, LW, tw, R, p, phisum, clr, o.g);
   // collision cost share: world hinge sum, plus the self-collision pairs
   // when that term is on
   float coll = P.wc * phisum;
-  if (P.ws != 0.f) {
+  if (EXT && P.ws != 0.f) {
     float selfsum = 0.f;
     self_collision<MODE>(rb, P, q, cp, LW, selfsum, clr, o.g);
     coll += P.ws * selfsum;
@@ -629,13 +684,13 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
 
 // The evaluation form for this team: PIPE when every lane holds at most one
 // sphere per link.
-template <int MODE>
+template <int MODE, bool EXT>
 __device__ __forceinline__ EvalOut eval_any(bool pipe, const RobotDev* __restrict__ rb,
                                             const ParamsDev& P, const Sampler& S, const Goal& goal,
                                             const float* q, int t, int T, int G, bool active,
                                             Team& tm) {
-  if (pipe) return evaluate<MODE, true>(rb, P, S, goal, q, t, T, G, active, tm);
-  return evaluate<MODE, false>(rb, P, S, goal, q, t, T, G, active, tm);
+  if (pipe) return evaluate<MODE, true, EXT>(rb, P, S, goal, q, t, T, G, active, tm);
+  return evaluate<MODE, false, EXT>(rb, P, S, goal, q, t, T, G, active, tm);
 }
 
 __device__ __forceinline__ bool use_pipe(const RobotDev* __restrict__ rb, const Team& tm, int G) {
@@ -787,8 +842,9 @@ __device__ __forceinline__ void trace_scalar(float* buf, const TileCtx& c, int k
 }
 
 // Final per-seed results and output trajectory.
-__device__ void finalize(const TileCtx& c, const float* x, Team& tm) {
-  EvalOut r = eval_any<EV_RESULT>(c.pipe, c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.G, c.active, tm);
+template <bool EXT>
+__device__ __forceinline__ void finalize(const TileCtx& c, const float* x, Team& tm) {
+  EvalOut r = eval_any<EV_RESULT, EXT>(c.pipe, c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.G, c.active, tm);
   float Jr = grp_sum(r.cost, c.G);
   float clr = grp_min(c.active ? r.clr : FLT_MAX, c.G);
   float perr = grp_sum((c.t == c.T - 1) ? r.perr : 0.f, c.G);
@@ -852,8 +908,8 @@ enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
 //          cost-only candidates while a seed of the tile has no Armijo step;
 //          if a seed accepted alpha < 1, evaluate there (ACCEPT), else update;
 //   ACCEPT take the accepted point's cost and gradient, update.
-template <bool LDS_HIST>
-__device__ __attribute__((noinline)) void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
+template <bool LDS_HIST, bool EXT>
+__device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
                          const ProbDev* __restrict__ probs, const TileDev& td, int max_iters,
                          Team& tm, float* hist_lds) {
   TileCtx c;
@@ -934,7 +990,7 @@ __device__ __attribute__((noinline)) void run_tile(const RobotDev* __restrict__ 
       phase = PH_TRIAL;
     }
     // the one cost+gradient evaluation of this pass
-    EvalOut e = eval_any<EV_GRAD>(c.pipe, rb, c.P, c.S, c.goal, xe, c.t, c.T, c.G, c.active, tm);
+    EvalOut e = eval_any<EV_GRAD, EXT>(c.pipe, rb, c.P, c.S, c.goal, xe, c.t, c.T, c.G, c.active, tm);
     ++evg;
     const float Je = grp_sum(e.cost, c.G);
     if (phase == PH_INIT) {
@@ -959,7 +1015,7 @@ __device__ __attribute__((noinline)) void run_tile(const RobotDev* __restrict__ 
         float xk[NJ];
 #pragma unroll
         for (int j = 0; j < NJ; ++j) xk[j] = x[j] + al * d[j];
-        EvalOut ek = eval_any<EV_COST>(c.pipe, rb, c.P, c.S, c.goal, xk, c.t, c.T, c.G, c.active,
+        EvalOut ek = eval_any<EV_COST, EXT>(c.pipe, rb, c.P, c.S, c.goal, xk, c.t, c.T, c.G, c.active,
                                        tm);
         ++evc;
         float Jk = grp_sum(ek.cost, c.G);
@@ -1039,18 +1095,18 @@ __device__ __attribute__((noinline)) void run_tile(const RobotDev* __restrict__ 
     trace_row(pb.tr_x, c, iter, x);
     trace_row(pb.tr_g, c, iter, g);
     trace_scalar(pb.tr_J, c, iter, J);
-    finalize(c, x, tm);
+    finalize<EXT>(c, x, tm);
   }
 }
 
-// Persistent optimiser: every wavefront takes tiles from an atomic counter
-// until the table is exhausted (tile_list, if given, indirects the table;
-// n_tiles_dev, if given, overrides n_tiles).
 // Persistent optimiser: every team (W = 1: every wavefront) takes tiles
 // from an atomic counter until the table is exhausted (tile_list, if given,
 // indirects the table; n_tiles_dev, if given, overrides n_tiles).  Every
 // member of a team sees the same tile sequence and the same decisions, so
-// all of them reach every barrier.
+// all of them reach every barrier.  Variants: TEAM (W > 1, history ring
+// in LDS) and EXT (self-collision and swept terms compiled in); the plain
+// variant carries no code for the optional terms.
+template <bool TEAM, bool EXT>
 __global__ void __launch_bounds__(MAX_TEAM * WAVE)
 k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
            const ProbDev* __restrict__ probs, const TileDev* __restrict__ tiles,
@@ -1061,13 +1117,13 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   const int lane = threadIdx.x & (WAVE - 1);
   const int nt = n_tiles_dev ? *n_tiles_dev : n_tiles;
   Team tm;
-  tm.W = pp->waves;
-  tm.w = (tm.W > 1) ? (int)(threadIdx.x / WAVE) : 0;
+  tm.W = TEAM ? pp->waves : 1;
+  tm.w = TEAM ? (int)(threadIdx.x / WAVE) : 0;
   tm.lds = s_dyn;
   tm.buf = 0;
   for (;;) {
     int mine = 0;
-    if (tm.W > 1) {
+    if constexpr (TEAM) {
       if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
       __syncthreads();
       mine = s_tile;
@@ -1079,11 +1135,11 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
     if (mine >= nt) break;
     const int ti = tile_list ? tile_list[mine] : mine;
     TileDev td = tiles[ti];
-    if (tm.W > 1) {
-      run_tile<true>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE);
+    if constexpr (TEAM) {
+      run_tile<true, EXT>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE);
       __syncthreads();   // the LDS ring is free for the next tile
     } else {
-      run_tile<false>(rb, pp, probs, td, max_iters, tm, nullptr);
+      run_tile<false, EXT>(rb, pp, probs, td, max_iters, tm, nullptr);
     }
   }
 }
@@ -1142,6 +1198,7 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
 
 // Objective (and gradient) of arbitrary trajectories: one wavefront per
 // seed group of G lanes (G = smallest of 16/32/64 holding T).
+template <bool EXT>
 __global__ void __launch_bounds__(BLOCK)
 k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const ProbDev* __restrict__ pb, const float* __restrict__ X, int S, int T, int G,
@@ -1166,7 +1223,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   for (int j = 0; j < NJ; ++j) x[j] = active ? X[((size_t)seed * T + t) * NJ + j] : 0.f;
   float J;
   if (with_grad) {
-    EvalOut e = eval_any<EV_GRAD>(use_pipe(rb, tm, G), rb, P, Sm, goal, x, t, T, G, active, tm);
+    EvalOut e = eval_any<EV_GRAD, EXT>(use_pipe(rb, tm, G), rb, P, Sm, goal, x, t, T, G, active, tm);
     J = grp_sum(e.cost, G);
     float w = dJ ? dJ[seed] : 1.f;
     if (active && owner) {
@@ -1174,7 +1231,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
       for (int j = 0; j < NJ; ++j) dX[((size_t)seed * T + t) * NJ + j] = w * e.g[j];
     }
   } else {
-    EvalOut e = eval_any<EV_COST>(use_pipe(rb, tm, G), rb, P, Sm, goal, x, t, T, G, active, tm);
+    EvalOut e = eval_any<EV_COST, EXT>(use_pipe(rb, tm, G), rb, P, Sm, goal, x, t, T, G, active, tm);
     J = grp_sum(e.cost, G);
   }
   if (J_out && lane == 0) J_out[seed] = J;
@@ -1182,6 +1239,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
 
 // Guidance: n gradient steps x <- x - alpha * g on every trajectory, one
 // wavefront per seed (same evaluation as the optimiser).
+template <bool EXT>
 __global__ void __launch_bounds__(BLOCK)
 k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
@@ -1205,12 +1263,12 @@ k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
 #pragma unroll
   for (int j = 0; j < NJ; ++j) x[j] = active ? X[((size_t)seed * T + t) * NJ + j] : 0.f;
   for (int k = 0; k < n_steps; ++k) {
-    EvalOut e = eval_any<EV_GRAD>(pipe, rb, P, Sm, goal, x, t, T, G, active, tm);
+    EvalOut e = eval_any<EV_GRAD, EXT>(pipe, rb, P, Sm, goal, x, t, T, G, active, tm);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) x[j] -= alpha * e.g[j];
   }
   if (J_out) {
-    EvalOut e = eval_any<EV_COST>(pipe, rb, P, Sm, goal, x, t, T, G, active, tm);
+    EvalOut e = eval_any<EV_COST, EXT>(pipe, rb, P, Sm, goal, x, t, T, G, active, tm);
     float J = grp_sum(e.cost, G);
     if (lane == 0) J_out[seed] = J;
   }
@@ -1340,30 +1398,38 @@ size_t team_lds(int W) {
   return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS) * sizeof(float) : 0;
 }
 
+using OptKernel = void (*)(const RobotDev*, const ParamsDev*, const ProbDev*, const TileDev*,
+                           const int*, const int*, int, int*, int);
+
+static OptKernel optimize_kernel(int W, bool ext) {
+  if (W > 1) return ext ? k_optimize<true, true> : k_optimize<true, false>;
+  return ext ? k_optimize<false, true> : k_optimize<false, false>;
+}
+
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
-                           int max_iters, int W, hipStream_t s) {
-  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(team_block(W)), team_lds(W), s, rb, pp,
-                     probs, tiles,
-                     (const int*)nullptr, (const int*)nullptr, n_tiles, counter, max_iters);
+                           int max_iters, int W, bool ext, hipStream_t s) {
+  hipLaunchKernelGGL(optimize_kernel(W, ext), dim3(grid_blocks), dim3(team_block(W)),
+                     team_lds(W), s, rb, pp, probs, tiles, (const int*)nullptr,
+                     (const int*)nullptr, n_tiles, counter, max_iters);
   return hipGetLastError();
 }
 
 hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                              const TileDev* tiles, const int* tile_list, int* counter,
-                             int max_tiles, int grid_blocks, int max_iters, int W,
+                             int max_tiles, int grid_blocks, int max_iters, int W, bool ext,
                              hipStream_t s) {
   // tile_list[0] holds the number of listed tiles, the indices follow
-  hipLaunchKernelGGL(k_optimize, dim3(grid_blocks), dim3(team_block(W)), team_lds(W), s, rb, pp,
-                     probs, tiles,
-                     tile_list + 1, tile_list, max_tiles, counter, max_iters);
+  hipLaunchKernelGGL(optimize_kernel(W, ext), dim3(grid_blocks), dim3(team_block(W)),
+                     team_lds(W), s, rb, pp, probs, tiles, tile_list + 1, tile_list, max_tiles,
+                     counter, max_iters);
   return hipGetLastError();
 }
 
-int optimize_blocks_per_cu(int W) {
+int optimize_blocks_per_cu(int W, bool ext) {
   int n = 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, k_optimize, team_block(W), team_lds(W)) !=
-      hipSuccess)
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, optimize_kernel(W, ext), team_block(W),
+                                                   team_lds(W)) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;
 }
@@ -1375,19 +1441,20 @@ hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipSt
 
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
-                       int with_grad, hipStream_t s) {
+                       int with_grad, bool ext, hipStream_t s) {
   int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
   int blocks = (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  hipLaunchKernelGGL(k_cost, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, dJ,
+  hipLaunchKernelGGL(ext ? k_cost<true> : k_cost<false>, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, dJ,
                      J_out, dX, with_grad);
   return hipGetLastError();
 }
 
 hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob, float* X,
-                        int S, int T, float alpha, int n_steps, float* J_out, hipStream_t s) {
+                        int S, int T, float alpha, int n_steps, float* J_out, bool ext,
+                        hipStream_t s) {
   int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
   int blocks = (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  hipLaunchKernelGGL(k_guide, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, alpha,
+  hipLaunchKernelGGL(ext ? k_guide<true> : k_guide<false>, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, alpha,
                      n_steps, J_out);
   return hipGetLastError();
 }

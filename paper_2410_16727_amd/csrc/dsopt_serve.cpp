@@ -238,7 +238,8 @@ int ds_serve_start(ds_plan* p, int max_slots, int queue_cap, void* stream) {
   hipError_t e1 = launch_zero_i32(sv->counter_dev, 1, sv->stream);
   hipError_t e2 = launch_serve_step(p->robot_dev, p->params_dev, sv->probs_dev, sv->tiles_dev,
                                     sv->tile_list_dev, sv->counter_dev, (int)max_tiles, grid,
-                                    p->params.block_iters, p->params.waves, sv->stream);
+                                    p->params.block_iters, p->params.waves,
+                                    params_ext(p->params), sv->stream);
   hipError_t e3 = launch_best(sv->probs_dev, max_slots, sv->slot_list_dev, sv->stream);
   hipError_t e4 = hipStreamEndCapture(sv->stream, &sv->graph);
   if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess || e4 != hipSuccess) {

@@ -59,7 +59,8 @@ class Params(C.Structure):
                 ("n_ls", C.c_int32), ("c1", C.c_float), ("delta0", C.c_float),
                 ("step_max", C.c_float), ("dt", C.c_float), ("tol_pos", C.c_float),
                 ("tol_rot", C.c_float), ("n_iters", C.c_int32), ("block_iters", C.c_int32),
-                ("waves_per_seed", C.c_int32), ("w_self", C.c_float)]
+                ("waves_per_seed", C.c_int32), ("w_self", C.c_float),
+                ("swept_samples", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -182,6 +183,7 @@ def params_struct(p: dict, n_iters: int, block_iters: int = 10):
     s.n_iters = int(n_iters); s.block_iters = int(block_iters)
     s.waves_per_seed = int(p.get("waves_per_seed", 1))
     s.w_self = float(p.get("w_self", 0.0))
+    s.swept_samples = int(p.get("swept_samples", 0))
     return s
 
 

@@ -21,11 +21,12 @@ DEFAULT = {
     "tol_pos": 0.005,          # success threshold delta_t [m] (Sec. 5.1)
     "tol_rot": 2.86 * math.pi / 180.0,   # success threshold delta_r [rad]
     "w_self": 0.0,             # self-collision weight (0: term off)
+    "swept_samples": 0,        # interpolated configurations per segment (0: waypoints only)
 }
 
 ORDER = ["w_collision", "eps", "lambda_v", "lambda_a", "lambda_j", "w_pos", "w_rot",
          "w_limit", "history", "n_ls", "c1", "delta0", "step_max", "dt", "tol_pos", "tol_rot",
-         "w_self"]
+         "w_self", "swept_samples"]
 
 
 def as_list(p=None):
