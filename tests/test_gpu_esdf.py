@@ -53,9 +53,16 @@ def test_full_size_shelf_grid_sampled():
                           rng.choice(np.flatnonzero(occ.reshape(-1)), 50, replace=False)])
     ref = oracle.esdf_from_occupancy(occ, sc.voxel, which=idx, threads=16)
     assert np.abs(d[idx] - ref).max() <= 2e-7 * np.abs(ref).max() + 1e-9
-    # the voxel distance field is close to the exact box distance (within a
+    # outside the boxes the scene's field (min over boxes) is the exact
+    # distance to their union and the voxel field lies within a voxel
+    # diagonal of it; inside overlapping boxes the min over boxes understates
+    # the depth, so there the voxel field is only at least as deep (less a
     # voxel diagonal)
-    assert np.abs(d.reshape(occ.shape) - sc.grid).max() < np.sqrt(3) * sc.voxel + 1e-6
+    d3 = d.reshape(occ.shape)
+    tol = np.sqrt(3) * sc.voxel + 1e-6
+    out_mask = sc.grid >= 0
+    assert np.abs(d3 - sc.grid)[out_mask].max() < tol
+    assert np.all(-d3[~out_mask] >= -sc.grid[~out_mask] - tol)
     prob = configs.problems("B")[0]
     seeds = torch.from_numpy(configs.seeds_for("B", 0, prob, S=8)).cuda()
     pl.optimize([{"scene": 0, "q_start": prob.q_start, "goal": prob.goal, "seeds": seeds,

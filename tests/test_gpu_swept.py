@@ -60,7 +60,7 @@ def test_swept_with_self_collision():
     robot = fat(key)
     scene = configs.scenes(key, only={0})[0]
     prob = configs.problems(key)[0]
-    plan = dsopt.Plan(robot, ps, 1, 256 << 20)
+    plan = dsopt.Plan(robot, ps, 1, 512 << 20)
     plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
     O = oracle.Oracle(robot, scene, params.as_list(ps), threads=8)
     X = gen.random_trajectories(np.random.default_rng(11), 8, 32, prob.q_start)
