@@ -234,7 +234,7 @@ def run_serving(args, dsopt, torch, configs, params):
     N = w.iters
     cells = sum((s.dims[0] - 1) * (s.dims[1] - 1) * (s.dims[2] - 1) for s in scenes)
     plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.serve_waves), N,
-                      cells * 32 + (3 << 30), block_iters=10)
+                      cells * 32 + (3 << 30), block_iters=args.serve_block)
     grids = [sc.grid for sc in scenes]
     for i, sc in enumerate(scenes):
         plan.upload_scene(i, sc.grid, sc.voxel, sc.origin)
@@ -311,7 +311,7 @@ def run_serving(args, dsopt, torch, configs, params):
     plan.close()
     return {"workload": (f"serving: Poisson {len(reqs)} requests at 200/s ({warm} warm-up), "
                          f"seeds U{{8..128}}, horizons U{{32..64}}, 16 resident 200^3 ESDFs, "
-                         f"{N} iters, blocks of 10 iterations per graph replay, "
+                         f"{N} iters, blocks of {args.serve_block} iterations per graph replay, "
                          f"{args.serve_slots} slots; served form {args.serve_waves} and plain "
                          f"serial form {args.serve_plain_waves} wavefronts per seed"),
             "served": served, "plain_serial": plain}
@@ -384,6 +384,8 @@ def main():
                     help="run one 256 MiB device copy (known traffic) for PMC scaling")
     ap.add_argument("--serve-requests", type=int, default=2200)
     ap.add_argument("--serve-slots", type=int, default=64)
+    ap.add_argument("--serve-block", type=int, default=10,
+                    help="iterations per graph replay in the served form")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this path has no multi-GPU form); got "
