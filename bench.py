@@ -222,7 +222,8 @@ def run_batched(args, dsopt, torch, configs, params):
 def run_serving(args, dsopt, torch, configs, params):
     """Poisson arrivals of mixed requests over 16 resident scenes: the
     served (continuous batching, graph-captured blocks) form vs the plain
-    serial form (FIFO, one request at a time, one launch each)."""
+    serial form (FIFO, one request at a time, one launch each), at the
+    workload's rate and at a rate above the plain form's capacity."""
     key = "E"
     w = configs.WORKLOADS[key]
     robot = configs.robot(key)
@@ -230,25 +231,28 @@ def run_serving(args, dsopt, torch, configs, params):
     scenes = configs.scenes(key, threads=host_threads())
     log(f"[bench] serving: built {len(scenes)} grids in {time.perf_counter() - t0:.1f} s")
     pool = configs.problems(key)
-    trace = configs.serving_trace(args.serve_requests)
     N = w.iters
     cells = sum((s.dims[0] - 1) * (s.dims[1] - 1) * (s.dims[2] - 1) for s in scenes)
-    plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.serve_waves), N,
-                      cells * 32 + (3 << 30), block_iters=args.serve_block)
-    grids = [sc.grid for sc in scenes]
-    for i, sc in enumerate(scenes):
-        plan.upload_scene(i, sc.grid, sc.voxel, sc.origin)
-    reqs = []
-    for r, (arr, pi, S, T) in enumerate(trace):
-        p = pool[pi]
-        sd = torch.from_numpy(configs.seeds_for(key, pi, p, S=S, T=T, stream=r)).cuda()
-        reqs.append({"arrival": arr, "S": S, "T": T,
-                     "spec": {"scene": p.scene, "q_start": p.q_start, "goal": p.goal,
-                              "seeds": sd}})
-    torch.cuda.synchronize()
-    warm = min(200, len(reqs) // 10)
 
-    def summarize(lat, done_t, name):
+    def make_plan(waves, block):
+        pl = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=waves), N,
+                        cells * 32 + (3 << 30), block_iters=block)
+        for i, sc in enumerate(scenes):
+            pl.upload_scene(i, sc.grid, sc.voxel, sc.origin)
+        return pl
+
+    def make_reqs(n, rate):
+        reqs = []
+        for r, (arr, pi, S, T) in enumerate(configs.serving_trace(n, rate)):
+            p = pool[pi]
+            sd = torch.from_numpy(configs.seeds_for(key, pi, p, S=S, T=T, stream=r)).cuda()
+            reqs.append({"arrival": arr, "S": S, "T": T,
+                         "spec": {"scene": p.scene, "q_start": p.q_start, "goal": p.goal,
+                                  "seeds": sd}})
+        torch.cuda.synchronize()
+        return reqs
+
+    def summarize(reqs, lat, done_t, name, warm):
         lat = np.array(lat[warm:])
         span = max(done_t[warm:]) - reqs[warm]["arrival"]
         out = {"p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -258,63 +262,75 @@ def run_serving(args, dsopt, torch, configs, params):
             f"{out['problems_per_s']:.1f} problems/s")
         return out
 
-    # served form
-    plan.serve_start(max_slots=args.serve_slots, queue_cap=len(reqs) + 1)
-    lat = [0.0] * len(reqs)
-    done_t = [0.0] * len(reqs)
-    pending = {}
-    i = 0
-    n_done = 0
-    start = time.perf_counter()
-    while n_done < len(reqs):
-        now = time.perf_counter() - start
-        while i < len(reqs) and reqs[i]["arrival"] <= now:
-            pending[plan.serve_submit(reqs[i]["spec"])] = i
-            i += 1
-        active = plan.serve_step()
-        for t, r in list(pending.items()):
-            res = plan.serve_poll(t)
-            if res is not None:
-                tt = time.perf_counter() - start
-                lat[r] = (tt - reqs[r]["arrival"]) * 1e3
-                done_t[r] = tt
-                del pending[t]
-                n_done += 1
-        if active == 0 and not pending and i < len(reqs):
-            time.sleep(max(0.0, reqs[i]["arrival"] - (time.perf_counter() - start)))
-    stats = plan.serve_stats()
-    plan.serve_stop()
-    served = summarize(lat, done_t, "served")
-    served["mean_active_slots"] = stats["mean_active_slots"]
-    served["graph_replays"] = stats["steps"]
-    # plain serial form: FIFO, one request at a time, each one launch, on a
-    # plan with its own best (latency) team size
-    plan.close()
-    plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.serve_plain_waves), N,
-                      cells * 32 + (3 << 30), block_iters=10)
-    for i, g in enumerate(grids):
-        plan.upload_scene(i, g, scenes[i].voxel, scenes[i].origin)
-    lat = [0.0] * len(reqs)
-    done_t = [0.0] * len(reqs)
-    start = time.perf_counter()
-    for r, rq in enumerate(reqs):
-        now = time.perf_counter() - start
-        if rq["arrival"] > now:
-            time.sleep(rq["arrival"] - now)
-        plan.optimize([dict(rq["spec"], tag=r + 1)])
-        plan.get_best(r + 1, rq["T"])
-        plan.release(r + 1)
-        tt = time.perf_counter() - start
-        lat[r] = (tt - rq["arrival"]) * 1e3
-        done_t[r] = tt
-    plain = summarize(lat, done_t, "plain serial")
-    plan.close()
-    return {"workload": (f"serving: Poisson {len(reqs)} requests at 200/s ({warm} warm-up), "
+    def served(plan, reqs, warm, name):
+        plan.serve_start(max_slots=args.serve_slots, queue_cap=len(reqs) + 1)
+        lat = [0.0] * len(reqs)
+        done_t = [0.0] * len(reqs)
+        pending = {}
+        i = 0
+        n_done = 0
+        start = time.perf_counter()
+        while n_done < len(reqs):
+            now = time.perf_counter() - start
+            while i < len(reqs) and reqs[i]["arrival"] <= now:
+                pending[plan.serve_submit(reqs[i]["spec"])] = i
+                i += 1
+            active = plan.serve_step()
+            for t, r in list(pending.items()):
+                res = plan.serve_poll(t)
+                if res is not None:
+                    tt = time.perf_counter() - start
+                    lat[r] = (tt - reqs[r]["arrival"]) * 1e3
+                    done_t[r] = tt
+                    del pending[t]
+                    n_done += 1
+            if active == 0 and not pending and i < len(reqs):
+                time.sleep(max(0.0, reqs[i]["arrival"] - (time.perf_counter() - start)))
+        stats = plan.serve_stats()
+        plan.serve_stop()
+        out = summarize(reqs, lat, done_t, name, warm)
+        out["mean_active_slots"] = stats["mean_active_slots"]
+        out["graph_replays"] = stats["steps"]
+        return out
+
+    def plain(plan, reqs, warm, name):
+        lat = [0.0] * len(reqs)
+        done_t = [0.0] * len(reqs)
+        start = time.perf_counter()
+        for r, rq in enumerate(reqs):
+            now = time.perf_counter() - start
+            if rq["arrival"] > now:
+                time.sleep(rq["arrival"] - now)
+            plan.optimize([dict(rq["spec"], tag=r + 1)])
+            plan.get_best(r + 1, rq["T"])
+            plan.release(r + 1)
+            tt = time.perf_counter() - start
+            lat[r] = (tt - rq["arrival"]) * 1e3
+            done_t[r] = tt
+        return summarize(reqs, lat, done_t, name, warm)
+
+    sp = make_plan(args.serve_waves, args.serve_block)
+    # plain serial form: on a plan with its own best (latency) team size
+    pp = make_plan(args.serve_plain_waves, 10)
+    out = {}
+    for tag, n, rate in (("rate", args.serve_requests, args.serve_rate),
+                         ("saturated", args.serve_sat_requests, args.serve_sat_rate)):
+        if n <= 0:
+            continue
+        reqs = make_reqs(n, rate)
+        warm = min(200, n // 10)
+        out[tag] = {
+            "workload": (f"serving: Poisson {n} requests at {rate:g}/s ({warm} warm-up), "
                          f"seeds U{{8..128}}, horizons U{{32..64}}, 16 resident 200^3 ESDFs, "
                          f"{N} iters, blocks of {args.serve_block} iterations per graph replay, "
                          f"{args.serve_slots} slots; served form {args.serve_waves} and plain "
                          f"serial form {args.serve_plain_waves} wavefronts per seed"),
-            "served": served, "plain_serial": plain}
+            "served": served(sp, reqs, warm, f"served @{rate:g}/s"),
+            "plain_serial": plain(pp, reqs, warm, f"plain serial @{rate:g}/s")}
+        del reqs
+    sp.close()
+    pp.close()
+    return out
 
 
 def run_esdf_build(args, dsopt, torch, configs, params, scene):
@@ -373,7 +389,7 @@ def main():
                     help="wavefronts per seed for the single-problem workload")
     ap.add_argument("--batched-waves", type=int, default=1,
                     help="wavefronts per seed for the batched workload")
-    ap.add_argument("--serve-waves", type=int, default=1,
+    ap.add_argument("--serve-waves", type=int, default=8,
                     help="wavefronts per seed for the served (batched) form")
     ap.add_argument("--serve-plain-waves", type=int, default=8,
                     help="wavefronts per seed for the plain serial form")
@@ -383,8 +399,14 @@ def main():
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy (known traffic) for PMC scaling")
     ap.add_argument("--serve-requests", type=int, default=2200)
+    ap.add_argument("--serve-rate", type=float, default=200.0,
+                    help="Poisson arrival rate of the serving workload [1/s]")
+    ap.add_argument("--serve-sat-requests", type=int, default=1000,
+                    help="requests of the saturated serving run (0: skip)")
+    ap.add_argument("--serve-sat-rate", type=float, default=2000.0,
+                    help="arrival rate of the saturated serving run [1/s]")
     ap.add_argument("--serve-slots", type=int, default=64)
-    ap.add_argument("--serve-block", type=int, default=10,
+    ap.add_argument("--serve-block", type=int, default=25,
                     help="iterations per graph replay in the served form")
     args = ap.parse_args()
     if args.gpus != 1:

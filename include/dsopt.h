@@ -285,11 +285,15 @@ int ds_serve_start(ds_plan* plan, int max_slots, int queue_cap, void* stream);
 /* Queue a request; `prob->seeds` must stay valid until its result is
  * polled.  DS_ERR_BUSY when the queue is full. */
 int ds_serve_submit(ds_plan* plan, const ds_problem* prob, uint64_t* ticket);
-/* Advance the loop by one step (admit, replay, retire).  Returns the number
- * of active slots after the step (>= 0) or an error. */
+/* Advance the loop by one step: collect completed replays, admit waiting
+ * requests, enqueue one replay (block_iters iterations of every active
+ * request).  Up to two replays are in flight; the call waits for the oldest
+ * only when both are.  Returns the number of requests in the enqueued
+ * replay (0: nothing to run) or an error. */
 int ds_serve_step(ds_plan* plan);
-/* Non-blocking: DS_OK with the result when done, DS_ERR_STATE when not yet,
- * DS_ERR_NOT_FOUND for an unknown ticket.  traj_host may be NULL. */
+/* Non-blocking (collects completed replays first): DS_OK with the result
+ * when done, DS_ERR_STATE when not yet, DS_ERR_NOT_FOUND for an unknown
+ * ticket.  traj_host (horizon x 7 floats) may be NULL. */
 int ds_serve_poll(ds_plan* plan, uint64_t ticket, ds_result* out, float* traj_host);
 int ds_serve_stats(ds_plan* plan, ds_latency_stats* out);
 int ds_serve_stop(ds_plan* plan);

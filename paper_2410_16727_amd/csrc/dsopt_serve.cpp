@@ -2,19 +2,28 @@
 //
 // Requests wait in a FIFO queue and are admitted into device slots while a
 // slot is free and the arena can hold the request's optimiser state.  One
-// step = retire the requests whose last iteration block has completed,
-// admit waiting ones, publish the active tile list, then replay a captured
-// HIP graph (counter reset kernel, persistent optimiser over the tile list
-// for block_iters iterations, best-seed kernel over the active slots).  The
+// step = collect the replays that have completed, admit waiting requests,
+// publish the active tile list, then enqueue a replay of a captured HIP
+// graph (counter reset kernel, persistent optimiser over the tile list for
+// block_iters iterations, best-seed kernel over the active slots).  The
 // graph is captured once with fixed arguments; membership changes only
 // through the device tables the host rewrites between replays, so requests
 // that arrive while others run overlap with them on the device.  Every
 // tile keeps its own state and iteration count, so a request's arithmetic
 // is the same as when it is optimised alone.
+//
+// A request's iteration count is fixed, so the host knows at enqueue time
+// which replay is a request's last: it queues the copy of the result to
+// pinned memory right behind that replay, frees the slot for the next
+// admission and defers the release of the request's arena memory to an
+// event after the copy.  Up to DEPTH replays are in flight, so the table
+// uploads and the next replay sit in the stream behind the running one and
+// the device does not wait for the host between blocks.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
 #include <cmath>
+#include <cstddef>
 #include <cstring>
 #include <deque>
 #include <map>
@@ -27,6 +36,30 @@ using namespace dsh;
 namespace {
 
 constexpr int MAX_TILES_PER_REQ = 128;
+constexpr int DEPTH = 2;   // replays in flight
+
+// pinned landing area of one finishing request, laid out like the device
+// outputs (result record padded to 256 bytes, best trajectory after it) so
+// one copy brings both
+struct Landing {
+  union {
+    ds_result result;
+    uint8_t pad[256];
+  };
+  float traj[DS_MAX_T * NJ];
+};
+static_assert(sizeof(ds_result) <= 256, "result record exceeds its slot");
+
+struct Finishing {
+  uint64_t ticket;
+  int slot;
+};
+
+struct Replay {
+  hipEvent_t done = nullptr;
+  int64_t seq = 0;
+  std::vector<Finishing> finishing;
+};
 
 struct ServeReq {
   ds_problem prob;
@@ -55,13 +88,15 @@ struct Serve {
   size_t tab_off = SIZE_MAX;
   ProbDev* probs_dev = nullptr;
   TileDev* tiles_dev = nullptr;
-  int* tile_list_dev = nullptr;   // [0] = count, then tile indices
   int* slot_list_dev = nullptr;   // [0] = count, then slot indices
+  int* tile_list_dev = nullptr;   // [0] = count, then tile indices (follows the slot list)
+  size_t slot_list_bytes = 0;     // padded size of the slot list region
+  bool lists_dirty = true;        // membership changed since the last upload
   int* counter_dev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  hipEvent_t replay_done = nullptr;
-  bool in_flight = false;
+  std::deque<Replay> inflight;
+  Landing* landing = nullptr;    // pinned, [DEPTH][max_slots]
   std::vector<Slot> slots;
   std::deque<uint64_t> queue;
   std::map<uint64_t, ServeReq> reqs;
@@ -71,13 +106,17 @@ struct Serve {
   double first_submit = -1, last_done = 0;
   int64_t steps = 0;
   double active_sum = 0;
-  std::vector<int> host_tiles, host_slots;
+  std::vector<int> host_lists, host_slots;
 };
 
 void ds_serve_free(ds_plan* p) {
   if (!p || !p->serve) return;
   Serve* sv = p->serve;
-  if (sv->in_flight) hipEventSynchronize(sv->replay_done);
+  for (Replay& r : sv->inflight) {
+    hipEventSynchronize(r.done);
+    put_event(p, r.done);
+  }
+  sv->inflight.clear();
   for (auto& sl : sv->slots) {
     if (sl.state_off != SIZE_MAX) p->arena.release(sl.state_off);
     if (sl.out_off != SIZE_MAX) p->arena.release(sl.out_off);
@@ -85,7 +124,7 @@ void ds_serve_free(ds_plan* p) {
   if (sv->tab_off != SIZE_MAX) p->arena.release(sv->tab_off);
   if (sv->exec) hipGraphExecDestroy(sv->exec);
   if (sv->graph) hipGraphDestroy(sv->graph);
-  if (sv->replay_done) hipEventDestroy(sv->replay_done);
+  if (sv->landing) hipHostFree(sv->landing);
   if (sv->own_stream) hipStreamDestroy(sv->stream);
   delete sv;
   p->serve = nullptr;
@@ -93,38 +132,32 @@ void ds_serve_free(ds_plan* p) {
 
 namespace {
 
-int retire(ds_plan* p, Serve* sv) {
-  if (!sv->in_flight) return DS_OK;
-  HIP_TRY(hipEventSynchronize(sv->replay_done));
-  sv->in_flight = false;
-  std::vector<int> finished;
-  for (int i = 0; i < sv->max_slots; ++i) {
-    Slot& sl = sv->slots[i];
-    if (!sl.ticket) continue;
-    ServeReq& r = sv->reqs[sl.ticket];
-    if (--r.blocks_left <= 0) finished.push_back(i);
-  }
-  for (int i : finished) {
-    Slot& sl = sv->slots[i];
-    ServeReq& r = sv->reqs[sl.ticket];
-    HIP_TRY(hipMemcpyAsync(&r.result, sl.result, sizeof(ds_result), hipMemcpyDeviceToHost,
-                           sv->stream));
-    r.best.resize((size_t)r.prob.horizon * NJ);
-    HIP_TRY(hipMemcpyAsync(r.best.data(), sl.best_traj, r.best.size() * sizeof(float),
-                           hipMemcpyDeviceToHost, sv->stream));
-  }
-  if (!finished.empty()) HIP_TRY(hipStreamSynchronize(sv->stream));
-  double t = now_s();
-  for (int i : finished) {
-    Slot& sl = sv->slots[i];
-    ServeReq& r = sv->reqs[sl.ticket];
-    r.done = true;
-    r.t_done = t;
-    sv->lat_ms.push_back((t - r.t_submit) * 1e3);
-    sv->last_done = t;
-    p->arena.release(sl.state_off);
-    p->arena.release(sl.out_off);
-    sl = Slot{};
+// Take the results of completed replays (in order).  With `block`, wait
+// for the oldest replay first.
+int collect(ds_plan* p, Serve* sv, bool block) {
+  while (!sv->inflight.empty()) {
+    Replay& rp = sv->inflight.front();
+    if (block) {
+      HIP_TRY(hipEventSynchronize(rp.done));
+      block = false;
+    } else {
+      hipError_t q = hipEventQuery(rp.done);
+      if (q == hipErrorNotReady) break;
+      if (q != hipSuccess) return fail(DS_ERR_HIP, "replay failed: %s", hipGetErrorString(q));
+    }
+    double t = now_s();
+    const Landing* set = sv->landing + (size_t)(rp.seq % DEPTH) * sv->max_slots;
+    for (const Finishing& f : rp.finishing) {
+      ServeReq& r = sv->reqs[f.ticket];
+      r.result = set[f.slot].result;
+      r.best.assign(set[f.slot].traj, set[f.slot].traj + (size_t)r.prob.horizon * NJ);
+      r.done = true;
+      r.t_done = t;
+      sv->lat_ms.push_back((t - r.t_submit) * 1e3);
+      sv->last_done = t;
+    }
+    put_event(p, rp.done);
+    sv->inflight.pop_front();
   }
   return DS_OK;
 }
@@ -157,6 +190,9 @@ int admit(ds_plan* p, Serve* sv) {
       sv->queue.pop_front();
       continue;
     }
+    if (reinterpret_cast<uint8_t*>(rec.best_traj) !=
+        reinterpret_cast<uint8_t*>(rec.result) + offsetof(Landing, traj))
+      return fail(DS_ERR_STATE, "output layout does not match the landing area");
     ProbDev pd = make_probdev(p, pr);
     pd.final_traj = rec.final_traj;
     pd.seed_res = rec.seed_res;
@@ -183,6 +219,7 @@ int admit(ds_plan* p, Serve* sv) {
     sl.best_traj = rec.best_traj;
     sl.ntiles = nt;
     r.slot = slot;
+    sv->lists_dirty = true;
     int B = std::max(1, p->params.block_iters);
     r.blocks_left = std::max(1, (p->params.n_iters + B - 1) / B);
     sv->queue.pop_front();
@@ -225,12 +262,18 @@ int ds_serve_start(ds_plan* p, int max_slots, int queue_cap, void* stream) {
   uint8_t* base = p->arena.ptr(sv->tab_off);
   sv->probs_dev = reinterpret_cast<ProbDev*>(base);
   sv->tiles_dev = reinterpret_cast<TileDev*>(base + a);
-  sv->tile_list_dev = reinterpret_cast<int*>(base + a + b);
-  sv->slot_list_dev = reinterpret_cast<int*>(base + a + b + c);
+  sv->slot_list_dev = reinterpret_cast<int*>(base + a + b);
+  sv->tile_list_dev = reinterpret_cast<int*>(base + a + b + d);
+  sv->slot_list_bytes = d;
   sv->counter_dev = reinterpret_cast<int*>(base + a + b + c + d);
   // empty lists before the first replay
   HIP_TRY(hipMemsetAsync(base, 0, a + b + c + d + 256, sv->stream));
-  HIP_TRY(hipEventCreateWithFlags(&sv->replay_done, hipEventDisableTiming));
+  if (hipHostMalloc((void**)&sv->landing, sizeof(Landing) * DEPTH * max_slots,
+                    hipHostMallocDefault) != hipSuccess) {
+    sv->landing = nullptr;
+    ds_serve_free(p);
+    return fail(DS_ERR_HIP, "pinned result area allocation failed");
+  }
   // capture one iteration block over whatever the tables hold at replay time
   int grid = std::max(1, p->cu_count * p->blocks_per_cu);
   HIP_TRY(hipStreamSynchronize(sv->stream));
@@ -277,30 +320,57 @@ int ds_serve_step(ds_plan* p) {
   if (!p) return fail(DS_ERR_INVALID, "NULL plan");
   Serve* sv = p->serve;
   if (!sv) return fail(DS_ERR_STATE, "serving not started");
-  if (int rc = retire(p, sv)) return rc;
+  if (int rc = collect(p, sv, (int)sv->inflight.size() >= DEPTH)) return rc;
+  poll_deferred(p, false);
   if (int rc = admit(p, sv)) return rc;
-  sv->host_tiles.assign(1, 0);
   sv->host_slots.assign(1, 0);
-  for (int i = 0; i < sv->max_slots; ++i) {
-    const Slot& sl = sv->slots[i];
-    if (!sl.ticket) continue;
-    sv->host_slots.push_back(i);
-    for (int k = 0; k < sl.ntiles; ++k) sv->host_tiles.push_back(i * MAX_TILES_PER_REQ + k);
-  }
+  for (int i = 0; i < sv->max_slots; ++i)
+    if (sv->slots[i].ticket) sv->host_slots.push_back(i);
   int active = (int)sv->host_slots.size() - 1;
   if (active == 0) return 0;
-  sv->host_tiles[0] = (int)sv->host_tiles.size() - 1;
   sv->host_slots[0] = active;
-  if (int rc = upload(p, sv->tile_list_dev, sv->host_tiles.data(),
-                      sv->host_tiles.size() * sizeof(int), sv->stream))
-    return rc;
-  if (int rc = upload(p, sv->slot_list_dev, sv->host_slots.data(),
-                      sv->host_slots.size() * sizeof(int), sv->stream))
-    return rc;
+  if (sv->lists_dirty) {
+    // slot list, then the tile list at its fixed offset: one upload, only
+    // when the membership changed
+    const size_t ns = sv->slot_list_bytes / sizeof(int);
+    sv->host_lists.assign(ns + 1, 0);
+    std::copy(sv->host_slots.begin(), sv->host_slots.end(), sv->host_lists.begin());
+    for (int i = 1; i <= active; ++i) {
+      const int slot = sv->host_slots[i];
+      for (int k = 0; k < sv->slots[slot].ntiles; ++k)
+        sv->host_lists.push_back(slot * MAX_TILES_PER_REQ + k);
+    }
+    sv->host_lists[ns] = (int)(sv->host_lists.size() - ns - 1);
+    if (int rc = upload(p, sv->slot_list_dev, sv->host_lists.data(),
+                        sv->host_lists.size() * sizeof(int), sv->stream))
+      return rc;
+    sv->lists_dirty = false;
+  }
   if (int rc = timed_launch(p, sv->stream, [&]() { return hipGraphLaunch(sv->exec, sv->stream); }))
     return rc;
-  HIP_TRY(hipEventRecord(sv->replay_done, sv->stream));
-  sv->in_flight = true;
+  Replay rp;
+  rp.seq = sv->steps;
+  Landing* set = sv->landing + (size_t)(rp.seq % DEPTH) * sv->max_slots;
+  for (int i = 1; i <= active; ++i) {
+    const int slot = sv->host_slots[i];
+    Slot& sl = sv->slots[slot];
+    ServeReq& r = sv->reqs[sl.ticket];
+    if (--r.blocks_left > 0) continue;
+    // last block of this request: land its result behind the replay, free
+    // the slot, release its memory once the copies are done
+    HIP_TRY(hipMemcpyAsync(&set[slot], sl.result,
+                           offsetof(Landing, traj) + (size_t)r.prob.horizon * NJ * sizeof(float),
+                           hipMemcpyDeviceToHost, sv->stream));
+    if (int rc = defer_free(p, sl.state_off, sv->stream)) return rc;
+    if (int rc = defer_free(p, sl.out_off, sv->stream)) return rc;
+    rp.finishing.push_back({sl.ticket, slot});
+    sl = Slot{};
+    sv->lists_dirty = true;
+  }
+  rp.done = get_event(p);
+  if (!rp.done) return fail(DS_ERR_HIP, "event creation failed");
+  HIP_TRY(hipEventRecord(rp.done, sv->stream));
+  sv->inflight.push_back(std::move(rp));
   sv->steps++;
   sv->active_sum += active;
   return active;
@@ -312,7 +382,10 @@ int ds_serve_poll(ds_plan* p, uint64_t ticket, ds_result* out, float* traj_host)
   if (!sv) return fail(DS_ERR_STATE, "serving not started");
   auto it = sv->reqs.find(ticket);
   if (it == sv->reqs.end()) return fail(DS_ERR_NOT_FOUND, "unknown ticket");
-  if (!it->second.done) return DS_ERR_STATE;
+  if (!it->second.done) {
+    if (int rc = collect(p, sv, false)) return rc;
+    if (!it->second.done) return DS_ERR_STATE;
+  }
   *out = it->second.result;
   if (traj_host && !it->second.best.empty())
     std::memcpy(traj_host, it->second.best.data(), it->second.best.size() * sizeof(float));

@@ -126,12 +126,13 @@ def test_full_batched_workload_flags_vs_oracle(batchD):
     say(f"checked {n_checked} sampled seeds")
 
 
-def test_serving_matches_alone_bitwise():
+@pytest.mark.parametrize("waves", [1, 8])
+def test_serving_matches_alone_bitwise(waves):
     key = "B"
     robot = configs.robot(key)
     scene = configs.scenes(key, only={0})[0]
     prob = configs.problems(key)[0]
-    plan = dsopt.Plan(robot, P, 30, 1 << 30, block_iters=7)
+    plan = dsopt.Plan(robot, dict(P, waves_per_seed=waves), 30, 1 << 30, block_iters=7)
     plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
     rng = np.random.default_rng(5)
     reqs = []
@@ -196,7 +197,7 @@ def test_serving_admission_waits_for_memory():
                                   "seeds": sd}) for _ in range(12)]
     max_active = 0
     left = set(tickets)
-    for _ in range(200):
+    for _ in range(20000):
         a = plan.serve_step()
         max_active = max(max_active, a)
         for t in list(left):
