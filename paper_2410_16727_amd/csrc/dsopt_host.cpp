@@ -255,6 +255,13 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
     // a fresh state: iteration counters start at zero
     HIP_TRY(hipMemsetAsync(p->arena.ptr(rec.state_off), 0, (size_t)nt * ST_BYTES, s));
   }
+  // longest tiles first: a tile's time grows with its group size (the
+  // spheres each lane walks), and the persistent grid drains the table in
+  // order, so the short tiles fill the tail instead of a long one starting
+  // last.  Per-seed arithmetic does not depend on the order.
+  if (n > 1)
+    std::stable_sort(td.begin(), td.end(),
+                     [](const TileDev& a, const TileDev& b) { return a.G > b.G; });
   uint8_t* tab = p->arena.ptr(launch->tab_off);
   ProbDev* pd_dev = reinterpret_cast<ProbDev*>(tab);
   size_t off_t = ((size_t)n * sizeof(ProbDev) + 255) / 256 * 256;

@@ -187,6 +187,18 @@ __device__ __forceinline__ float4 load_rec(const Sampler& S, int off) {
 
 enum { EV_COST = 0, EV_GRAD = 1, EV_RESULT = 2 };
 
+// The robot's sphere table (offset, radius; sorted by link) staged in LDS
+// by every kernel that evaluates the objective: the sphere a lane takes
+// depends on its copy index, so the reads are per-lane and would otherwise
+// be vector memory round trips ahead of every record gather.
+__shared__ float4 s_sph[DS_MAX_SPHERES];
+
+// Fill s_sph; every thread of the workgroup must call it.
+__device__ __forceinline__ void stage_spheres(const RobotDev* __restrict__ rb) {
+  for (int i = threadIdx.x; i < rb->ns; i += blockDim.x) s_sph[i] = rb->sph[i];
+  __syncthreads();
+}
+
 // Joint twists (axis z_i, origin o_i) of the swept joints, kept for the
 // wrench projections of the adjoint.
 struct Twists {
@@ -350,7 +362,7 @@ __device__ __attribute__((noinline)) void self_collision(const RobotDev* __restr
       const int b0 = rb->link_begin[lb], nb = rb->link_begin[lb + 1] - b0;
       for (int k = cp; k < na * nb; k += LW) {
         const int ia = k / nb, ib = k - ia * nb;
-        const float4 sa = rb->sph[a0 + ia], sb = rb->sph[b0 + ib];
+        const float4 sa = s_sph[a0 + ia], sb = s_sph[b0 + ib];
         float ca[3], cb[3];
 #pragma unroll
         for (int r = 0; r < 3; ++r) {
@@ -447,7 +459,7 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
       const int sk = s0 + cp;
       pv_[l] = sk < s1;
       if (pv_[l]) {
-        float4 sp = rb->sph[sk];
+        float4 sp = s_sph[sk];
         pc_[l][0] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
         pc_[l][1] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
         pc_[l][2] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
@@ -470,7 +482,7 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
       for (int k = 0; k < CH; ++k) {
         const int sk = s + k * LW + cp;
         if (sk < s1) {
-          float4 sp = rb->sph[sk];
+          float4 sp = s_sph[sk];
           cxs[k] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
           cys[k] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
           czs[k] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
@@ -768,18 +780,28 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
   float q[NJ], a[DS_MAX_HISTORY];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) q[j] = g[j];
+  // the slot loads of step k+1 are issued before step k's reduction, so
+  // one memory latency overlaps each dependent dot product
+  float sn[NJ], yn[NJ], rn = 0.f;
+  auto fetch = [&](int k) {
+    const int slot = (head - 1 - k + 2 * m) % m;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      sn[j] = hist.s(slot, j);
+      yn[j] = hist.y(slot, j);
+    }
+    rn = hist.rho(slot);
+  };
+  if (cmax > 0) fetch(0);
 #pragma unroll
   for (int k = 0; k < DS_MAX_HISTORY; ++k) {
     a[k] = 0.f;
     if (k < cmax) {
-      int slot = (head - 1 - k + 2 * m) % m;
       float s[NJ], y[NJ];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        s[j] = hist.s(slot, j);
-        y[j] = hist.y(slot, j);
-      }
-      float rho = hist.rho(slot);
+      for (int j = 0; j < NJ; ++j) { s[j] = sn[j]; y[j] = yn[j]; }
+      const float rho = rn;
+      if (k + 1 < cmax) fetch(k + 1);
       float dt = grp_sum(dot7(s, q), c.G);
       bool use = k < cnt;
       float ak = rho * dt;
@@ -794,17 +816,15 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
   float gamma = 1.f / (rho_n * yy_n);   // s^T y / y^T y
 #pragma unroll
   for (int j = 0; j < NJ; ++j) q[j] *= gamma;
+  if (cmax > 0) fetch(cmax - 1);
 #pragma unroll
   for (int k = DS_MAX_HISTORY - 1; k >= 0; --k) {
     if (k < cmax) {
-      int slot = (head - 1 - k + 2 * m) % m;
       float s[NJ], y[NJ];
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) {
-        s[j] = hist.s(slot, j);
-        y[j] = hist.y(slot, j);
-      }
-      float rho = hist.rho(slot);
+      for (int j = 0; j < NJ; ++j) { s[j] = sn[j]; y[j] = yn[j]; }
+      const float rho = rn;
+      if (k > 0) fetch(k - 1);
       float b = rho * grp_sum(dot7(y, q), c.G);
       bool use = k < cnt;
 #pragma unroll
@@ -1114,6 +1134,7 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
            int* counter, int max_iters) {
   extern __shared__ float s_dyn[];
   __shared__ int s_tile;
+  stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
   const int nt = n_tiles_dev ? *n_tiles_dev : n_tiles;
   Team tm;
@@ -1204,6 +1225,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const ProbDev* __restrict__ pb, const float* __restrict__ X, int S, int T, int G,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
        int with_grad) {
+  stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
   const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
   if (seed >= S) return;   // whole wavefront past the end
@@ -1244,6 +1266,7 @@ __global__ void __launch_bounds__(BLOCK)
 k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
         int n_steps, float* __restrict__ J_out) {
+  stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
   const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
   if (seed >= S) return;   // whole wavefront past the end
