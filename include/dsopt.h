@@ -115,6 +115,12 @@ typedef struct ds_params {
                             are interpolated linearly), add to C_world and to the
                             clearance; their gradient splits (1 - tau, tau) onto
                             the two waypoints.  0: waypoints only. */
+  int32_t exact_gathers; /* 0 (default): a sphere sample whose cell lies in a block
+                            of the scene's coarse minimum-distance table that
+                            clears the sphere by more than eps is not gathered --
+                            its hinge and gradient are exactly zero, so results
+                            are the same bit for bit.  1: gather every sample
+                            (for verifying that equality). */
 } ds_params;
 
 /* One planning problem (Sec. 3).  `seeds` are the seed trajectories
@@ -152,7 +158,9 @@ typedef struct ds_seed_result {
   int32_t collision_free, within_limits, success, valid;
   int32_t n_evals_cost;    /* cost-only evaluations run for this seed's wavefront */
   int32_t n_evals_grad;    /* cost+gradient evaluations run for this seed's wavefront */
-  int32_t pad;
+  uint32_t n_gathers;      /* ESDF cell records (32 B each) gathered for this seed,
+                              over all its wavefronts and launches; the coarse
+                              table's skips are not counted */
 } ds_seed_result;
 
 typedef struct ds_plan ds_plan;

@@ -235,6 +235,8 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
       cleanup();
       return rc;
     }
+    // per-seed gather counters accumulate over launches
+    HIP_TRY(hipMemsetAsync(rec.seed_res, 0, (size_t)rec.S * sizeof(ds_seed_result), s));
     pd[i] = make_probdev(p, pr);
     pd[i].final_traj = rec.final_traj;
     pd[i].seed_res = rec.seed_res;
@@ -371,6 +373,10 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   P.m = prm->history; P.nls = prm->n_ls; P.n_iters = prm->n_iters; P.block_iters = prm->block_iters;
   P.waves = prm->waves_per_seed;
   P.nsub = prm->swept_samples;
+  // float32 trilinear blends stay within 1e-6 of their corner range for
+  // distances of metres; the margin keeps the zero-hinge proof exact
+  P.far = prm->eps + 1e-5f;
+  P.skip = prm->exact_gathers ? 0 : 1;
   p->blocks_per_cu = optimize_blocks_per_cu(P.waves, params_ext(P));
 
   p->robot_off = p->arena.alloc(sizeof(RobotDev));
@@ -416,7 +422,18 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
     p->arena.release(p->scenes[scene_id].off);
     p->scenes.erase(scene_id);
   }
-  size_t off = arena_alloc(p, rec_bytes);
+  // coarse block size: the smallest 2^s (s >= 2) cells per axis whose table
+  // fits COARSE_MAX blocks
+  int cshift = 2, cdx, cdy, cdz;
+  for (;; ++cshift) {
+    const int b = 1 << cshift;
+    cdx = (nx - 1 + b - 1) / b;
+    cdy = (ny - 1 + b - 1) / b;
+    cdz = (nz - 1 + b - 1) / b;
+    if ((long long)cdx * cdy * cdz <= COARSE_MAX) break;
+  }
+  const size_t coarse_at = (rec_bytes + 255) / 256 * 256;
+  size_t off = arena_alloc(p, coarse_at + COARSE_MAX * sizeof(float));
   if (off == SIZE_MAX) return fail(DS_ERR_NOMEM, "arena full (scene %d, %zu B)", scene_id, rec_bytes);
   const float* src = vals;
   size_t tmp_off = SIZE_MAX;
@@ -436,6 +453,8 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
     src = reinterpret_cast<const float*>(p->arena.ptr(tmp_off));
   }
   HIP_TRY(launch_esdf_pack(src, nx, ny, nz, reinterpret_cast<float4*>(p->arena.ptr(off)), s));
+  float* coarse = reinterpret_cast<float*>(p->arena.ptr(off) + coarse_at);
+  HIP_TRY(launch_coarse(src, nx, ny, nz, cshift, cdx, cdy, cdz, coarse, s));
   if (tmp_off != SIZE_MAX)
     if (int rc = defer_free(p, tmp_off, s)) return rc;
   SceneRec rec;
@@ -445,6 +464,9 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
   rec.dev.ox = origin[0]; rec.dev.oy = origin[1]; rec.dev.oz = origin[2];
   rec.dev.inv_h = 1.f / voxel;
   rec.dev.bytes = (uint32_t)rec_bytes;
+  rec.dev.coarse = coarse;
+  rec.dev.cshift = cshift;
+  rec.dev.cdx = cdx; rec.dev.cdy = cdy; rec.dev.cdz = cdz;
   p->scenes[scene_id] = rec;
   return DS_OK;
 }

@@ -32,15 +32,24 @@ struct ParamsDev {
   int32_t m, nls, n_iters, block_iters;
   int32_t waves;         // wavefronts per seed (1, 2, 4 or 8)
   int32_t nsub;          // swept sub-samples per segment
+  float far;             // a block minimum >= radius + far proves a zero hinge
+  int32_t skip;          // use the coarse table (0: gather every sample)
 };
 
 // One resident scene: the 8 corners of cell (i,j,k) are the 32-byte record
 // i + (nx-1)*(j + (ny-1)*k): [c000 c100 c010 c110 | c001 c101 c011 c111].
+// Coarse table: the minimum node distance over each block of 2^cshift
+// cells per axis (node range of the block's cells, inclusive), at most
+// COARSE_MAX blocks, x fastest.
+constexpr int COARSE_MAX = 4096;
+
 struct SceneDev {
   const float4* rec;
   int32_t nx, ny, nz;    // node counts
   float ox, oy, oz, inv_h;
   uint32_t bytes;        // size of the record array
+  const float* coarse;   // [cdz][cdy][cdx] block minima
+  int32_t cshift, cdx, cdy, cdz;
 };
 
 struct ProbDev {
@@ -101,6 +110,8 @@ namespace dsk {
 inline bool params_ext(const ParamsDev& P) { return P.ws != 0.f || P.nsub > 0; }
 hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* rec,
                             hipStream_t s);
+hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
+                         int cdz, float* out, hipStream_t s);
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
                            int max_iters, int waves, bool ext, hipStream_t s);

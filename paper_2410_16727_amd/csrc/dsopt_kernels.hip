@@ -40,6 +40,13 @@ template <class T>
 __device__ __forceinline__ const DS_GLOBAL T* glb(const T* p) {
   return (const DS_GLOBAL T*)p;
 }
+// ... and that a pointer into a __shared__ array addresses LDS (ds_read /
+// ds_write rather than flat accesses).
+#define DS_LDS __attribute__((address_space(3)))
+template <class T>
+__device__ __forceinline__ DS_LDS T* lds(T* p) {
+  return (DS_LDS T*)p;
+}
 #ifndef DSOPT_CH
 #define DSOPT_CH 2
 #endif
@@ -107,6 +114,8 @@ struct Sampler {
   __amdgpu_buffer_rsrc_t rsrc;
   float ox, oy, oz, inv_h, nxm1, nym1, nzm1;
   int nxm2, nym2, nzm2, cx, cy;    // cells along x and y
+  const DS_LDS float* cm;          // the scene's coarse table, staged in LDS
+  int cshift, cdx, cdy;
 };
 
 __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
@@ -117,7 +126,20 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
   s.nxm2 = sc.nx - 2; s.nym2 = sc.ny - 2; s.nzm2 = sc.nz - 2;
   s.cx = sc.nx - 1;
   s.cy = sc.ny - 1;
+  s.cm = nullptr;
+  s.cshift = sc.cshift;
+  s.cdx = sc.cdx;
+  s.cdy = sc.cdy;
   return s;
+}
+
+// Copy the scene's coarse table into LDS (threads tid = 0..nth-1 of the
+// group that shares it; the caller synchronises them afterwards).
+__device__ __forceinline__ void stage_coarse(const SceneDev& sc, DS_LDS float* dst, int tid,
+                                             int nth) {
+  const int n = sc.cdx * sc.cdy * sc.cdz;
+  const DS_GLOBAL float* src = glb(sc.coarse);
+  for (int i = tid; i < n; i += nth) dst[i] = src[i];
 }
 
 // Cell lookup for a query point: clamp u = (p - origin) / voxel into the
@@ -125,6 +147,7 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
 // axes were inside (gradient is zero along clamped axes).
 struct Cell {
   int off;            // byte offset of the cell's 32-byte record
+  int cidx;           // the cell's block in the coarse table
   float fx, fy, fz;
   float mx, my, mz;   // 1/voxel inside the grid along the axis, 0 when clamped
 };
@@ -152,7 +175,17 @@ __device__ __forceinline__ Cell locate(const Sampler& S, float px, float py, flo
   // record index ix + cx*(iy + cy*iz); every factor fits 24 bits
   unsigned row = __umul24((unsigned)S.cy, (unsigned)iz) + (unsigned)iy;
   c.off = (int)((__umul24((unsigned)S.cx, row) + (unsigned)ix) << 5);
+  unsigned crow = __umul24((unsigned)S.cdy, (unsigned)(iz >> S.cshift)) + (unsigned)(iy >> S.cshift);
+  c.cidx = (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
   return c;
+}
+
+// True when the coarse table proves the sample's hinge is zero: every
+// corner of every cell in the block is at least radius + eps (+ margin)
+// from the nearest obstacle, and a trilinear blend stays within its corner
+// range.
+__device__ __forceinline__ bool far_sample(const Sampler& S, const Cell& c, float r, float far) {
+  return S.cm[c.cidx] >= r + far;
 }
 
 // Trilinear blend of a cell record (a: z0 corners, b: z1 corners) and, with
@@ -218,6 +251,7 @@ struct EvalOut {
   float g[NJ];       // gradient row (EV_GRAD; zero at t = 0 and inactive lanes)
   float clr;         // min (distance - radius) at this waypoint (EV_RESULT)
   float perr, rerr;  // goal errors at this lane's waypoint (EV_RESULT)
+  int ng;            // cell records this lane gathered
 };
 
 // Smoothness on the lane group: v_t = q_{t+1} - q_t (t <= T-2),
@@ -423,8 +457,11 @@ template <int MODE, bool PIPE>
 __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const ParamsDev& P,
                                       const Sampler& S, const float* q, int cp, int LW,
                                       Twists& tw, float* R, float* p, float& phisum, float& clr,
-                                      float* g) {
+                                      float* g, int& ng, bool active) {
   constexpr bool GRAD = (MODE == EV_GRAD);
+  // the result pass gathers every sample: the clearance is a minimum over
+  // all of them
+  const bool SKIP = MODE != EV_RESULT && P.skip;
   R[0] = 1.f; R[1] = 0.f; R[2] = 0.f; R[3] = 0.f; R[4] = 1.f; R[5] = 0.f;
   R[6] = 0.f; R[7] = 0.f; R[8] = 1.f;
   p[0] = p[1] = p[2] = 0.f;
@@ -457,7 +494,7 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
     const int s0 = rb->link_begin[l], s1 = rb->link_begin[l + 1];
     if (PIPE) {
       const int sk = s0 + cp;
-      pv_[l] = sk < s1;
+      pv_[l] = active && sk < s1;   // lanes past the horizon gather nothing
       if (pv_[l]) {
         float4 sp = s_sph[sk];
         pc_[l][0] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
@@ -465,8 +502,13 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
         pc_[l][2] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
         pr_[l] = sp.w;
         Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
-        pa_[l] = load_rec(S, cl.off);
-        pz_[l] = load_rec(S, cl.off + 16);
+        if (SKIP && far_sample(S, cl, sp.w, P.far)) {
+          pv_[l] = false;   // zero hinge, zero gradient: nothing to add
+        } else {
+          pa_[l] = load_rec(S, cl.off);
+          pz_[l] = load_rec(S, cl.off + 16);
+          ++ng;
+        }
       }
       continue;
     }
@@ -478,23 +520,30 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
       Cell cl[CH];
       float4 ra[CH], rz[CH];
       float cxs[CH], cys[CH], czs[CH], rr[CH];
+      bool use[CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int sk = s + k * LW + cp;
-        if (sk < s1) {
+        use[k] = active && sk < s1;
+        if (use[k]) {
           float4 sp = s_sph[sk];
           cxs[k] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
           cys[k] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
           czs[k] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
           rr[k] = sp.w;
           cl[k] = locate(S, cxs[k], cys[k], czs[k]);
-          ra[k] = load_rec(S, cl[k].off);
-          rz[k] = load_rec(S, cl[k].off + 16);
+          if (SKIP && far_sample(S, cl[k], sp.w, P.far)) {
+            use[k] = false;   // zero hinge, zero gradient
+          } else {
+            ra[k] = load_rec(S, cl[k].off);
+            rz[k] = load_rec(S, cl[k].off + 16);
+            ++ng;
+          }
         }
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
-        if (s + k * LW + cp < s1)
+        if (use[k])
           sphere_term<MODE>(P, S, cl[k], ra[k], rz[k], rr[k], cxs[k], cys[k], czs[k], phisum,
                             clr, FM);
       }
@@ -531,6 +580,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   const int cp = tm.w * L + lane / G;
   const int LW = tm.W * L;
   EvalOut o;
+  o.ng = 0;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) o.g[j] = 0.f;
   float phisum = 0.f, clr = FLT_MAX;
@@ -554,7 +604,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       }
       Twists tws;
       float ph = 0.f, cl = FLT_MAX;
-      sweep<MODE, PIPE>(rb, P, S, qi, cp, LW, tws, Rs, ps, ph, cl, gi);
+      sweep<MODE, PIPE>(rb, P, S, qi, cp, LW, tws, Rs, ps, ph, cl, gi, o.ng, seg);
       if (seg) {
         phisum += ph;
         clr = fminf(clr, cl);
@@ -575,7 +625,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   }
   float R[9], p[3];
   Twists tw;
-  sweep<MODE, PIPE>(rb, P, S, q, cp, LW, tw, R, p, phisum, clr, o.g);
+  sweep<MODE, PIPE>(rb, P, S, q, cp, LW, tw, R, p, phisum, clr, o.g, o.ng, active);
   // collision cost share: world hinge sum, plus the self-collision pairs
   // when that term is on
   float coll = P.wc * phisum;
@@ -863,7 +913,7 @@ __device__ __forceinline__ void trace_scalar(float* buf, const TileCtx& c, int k
 
 // Final per-seed results and output trajectory.
 template <bool EXT>
-__device__ __forceinline__ void finalize(const TileCtx& c, const float* x, Team& tm) {
+__device__ __forceinline__ int finalize(const TileCtx& c, const float* x, Team& tm) {
   EvalOut r = eval_any<EV_RESULT, EXT>(c.pipe, c.rb, c.P, c.S, c.goal, x, c.t, c.T, c.G, c.active, tm);
   float Jr = grp_sum(r.cost, c.G);
   float clr = grp_min(c.active ? r.clr : FLT_MAX, c.G);
@@ -907,15 +957,15 @@ __device__ __forceinline__ void finalize(const TileCtx& c, const float* x, Team&
                   rerr < c.P.tol_rot) ? 1 : 0;
     sr.n_evals_cost = ((const DS_GLOBAL int*)c.st)[ST_EVC + c.lane];
     sr.n_evals_grad = ((const DS_GLOBAL int*)c.st)[ST_EVG + c.lane];
-    sr.pad = 0;
     // field by field: the implicit struct copy has no global-address form
     DS_GLOBAL ds_seed_result* o = glb(c.pb->seed_res) + c.seed;
     o->cost = sr.cost; o->clearance = sr.clearance; o->pos_err = sr.pos_err;
     o->rot_err = sr.rot_err; o->max_jerk = sr.max_jerk;
     o->collision_free = sr.collision_free; o->within_limits = sr.within_limits;
     o->success = sr.success; o->valid = sr.valid; o->n_evals_cost = sr.n_evals_cost;
-    o->n_evals_grad = sr.n_evals_grad; o->pad = 0;
+    o->n_evals_grad = sr.n_evals_grad;
   }
+  return r.ng;
 }
 
 enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
@@ -931,7 +981,7 @@ enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
 template <bool LDS_HIST, bool EXT>
 __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
                          const ProbDev* __restrict__ probs, const TileDev& td, int max_iters,
-                         Team& tm, float* hist_lds) {
+                         Team& tm, float* hist_lds, float* coarse_lds) {
   TileCtx c;
   c.rb = rb;
   c.P = *pp;
@@ -955,6 +1005,7 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
   float x[NJ], g[NJ], d[NJ], xe[NJ], gt[NJ];
   float J = 0.f, Jt = 0.f, gtd = 0.f, alpha = 0.f;
   int cnt, head, evc, evg, chosen = 0;
+  int ngath = 0;   // cell records gathered by this lane in this launch
   int iter = sti[ST_ITER + c.lane];
   int phase;
   if (iter == 0) {
@@ -985,15 +1036,20 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
   // the history ring: LDS copy for a team, else the tile state
   typename std::conditional<LDS_HIST, LHist, GHist>::type hist;
   hist.lane = c.lane;
+  // the scene's coarse table: shared by the team, else this wavefront's own
+  c.S.cm = lds(coarse_lds);
   if constexpr (LDS_HIST) {
     hist.h = hist_lds;
     if (iter > 0 && n_left > 0) {   // resume: bring the ring into LDS
       const DS_GLOBAL float* src = c.st + ST_RHO;
       for (int i = threadIdx.x; i < H_FLOATS; i += tm.W * WAVE) hist_lds[i] = src[i];
     }
+    if (c.P.skip) stage_coarse(pb.sc, lds(coarse_lds), threadIdx.x, tm.W * WAVE);
     tm.sync();
   } else {
     hist.h = c.st + ST_RHO;
+    // one wavefront: its LDS accesses complete in order, no barrier needed
+    if (c.P.skip) stage_coarse(pb.sc, lds(coarse_lds), c.lane, WAVE);
   }
 
   for (;;) {
@@ -1012,6 +1068,7 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
     // the one cost+gradient evaluation of this pass
     EvalOut e = eval_any<EV_GRAD, EXT>(c.pipe, rb, c.P, c.S, c.goal, xe, c.t, c.T, c.G, c.active, tm);
     ++evg;
+    ngath += e.ng;
     const float Je = grp_sum(e.cost, c.G);
     if (phase == PH_INIT) {
 #pragma unroll
@@ -1038,6 +1095,7 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
         EvalOut ek = eval_any<EV_COST, EXT>(c.pipe, rb, c.P, c.S, c.goal, xk, c.t, c.T, c.G, c.active,
                                        tm);
         ++evc;
+        ngath += ek.ng;
         float Jk = grp_sum(ek.cost, c.G);
         if (need && Jk <= J + c.P.c1 * al * gtd) chosen = kk;
         if (need && Jk < Jmin) { Jmin = Jk; kmin = kk; }
@@ -1115,8 +1173,14 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
     trace_row(pb.tr_x, c, iter, x);
     trace_row(pb.tr_g, c, iter, g);
     trace_scalar(pb.tr_J, c, iter, J);
-    finalize<EXT>(c, x, tm);
+    ngath += finalize<EXT>(c, x, tm);
   }
+  // this launch's gathers into the seed's counter: every lane adds its own
+  // count.  No lane-dependent branch here -- one at the end of the tile body
+  // turns the persistent tile loop into a divergent loop, and the wavefront's
+  // tile fetch below must run with the whole wavefront.
+  __hip_atomic_fetch_add(&glb(pb.seed_res)[c.seed].n_gathers, (unsigned)ngath,
+                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Persistent optimiser: every team (W = 1: every wavefront) takes tiles
@@ -1150,17 +1214,22 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
       mine = s_tile;
       __syncthreads();
     } else {
-      if (lane == 0) mine = atomicAdd(counter, 1);
-      mine = __builtin_amdgcn_readfirstlane(__shfl(mine, 0));
+      // one increment per wavefront, by its first active lane, broadcast
+      // from that lane (correct for any set of active lanes)
+      const int first = __ffsll((long long)__ballot(1)) - 1;
+      if (lane == first) mine = atomicAdd(counter, 1);
+      mine = __builtin_amdgcn_readfirstlane(__shfl(mine, first));
     }
     if (mine >= nt) break;
     const int ti = tile_list ? tile_list[mine] : mine;
     TileDev td = tiles[ti];
     if constexpr (TEAM) {
-      run_tile<true, EXT>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE);
+      run_tile<true, EXT>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE,
+                          s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS);
       __syncthreads();   // the LDS ring is free for the next tile
     } else {
-      run_tile<false, EXT>(rb, pp, probs, td, max_iters, tm, nullptr);
+      run_tile<false, EXT>(rb, pp, probs, td, max_iters, tm, nullptr,
+                           s_dyn + (threadIdx.x / WAVE) * COARSE_MAX);
     }
   }
 }
@@ -1225,6 +1294,8 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const ProbDev* __restrict__ pb, const float* __restrict__ X, int S, int T, int G,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
        int with_grad) {
+  __shared__ float s_cm[COARSE_MAX];
+  if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
   const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
@@ -1234,6 +1305,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   const bool active = t < T;
   ParamsDev P = *pp;
   Sampler Sm = make_sampler(pb->sc);
+  Sm.cm = lds(s_cm);
   Goal goal = make_goal(*pb);
   Team tm;
   tm.W = 1;
@@ -1266,6 +1338,8 @@ __global__ void __launch_bounds__(BLOCK)
 k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
         int n_steps, float* __restrict__ J_out) {
+  __shared__ float s_cm[COARSE_MAX];
+  if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
   const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
@@ -1275,6 +1349,7 @@ k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   const bool active = t < T;
   ParamsDev P = *pp;
   Sampler Sm = make_sampler(pb->sc);
+  Sm.cm = lds(s_cm);
   Goal goal = make_goal(*pb);
   Team tm;
   tm.W = 1;
@@ -1354,6 +1429,26 @@ __global__ void k_esdf_pack(const float* __restrict__ v, int nx, int ny, int nz,
   }
 }
 
+// Coarse table: minimum node value over each block of 2^shift cells per axis
+// (the nodes of the block's cells, inclusive of the far faces), one thread
+// per block.
+__global__ void k_coarse(const float* __restrict__ v, int nx, int ny, int nz, int shift, int cdx,
+                         int cdy, int cdz, float* __restrict__ out) {
+  const int b = blockIdx.x * blockDim.x + threadIdx.x;
+  if (b >= cdx * cdy * cdz) return;
+  const int bx = b % cdx, by = (b / cdx) % cdy, bz = b / (cdx * cdy);
+  const int x0 = bx << shift, x1 = min((bx + 1) << shift, nx - 1);
+  const int y0 = by << shift, y1 = min((by + 1) << shift, ny - 1);
+  const int z0 = bz << shift, z1 = min((bz + 1) << shift, nz - 1);
+  float m = FLT_MAX;
+  for (int k = z0; k <= z1; ++k)
+    for (int j = y0; j <= y1; ++j) {
+      const float* row = v + (size_t)nx * (j + (size_t)ny * k);
+      for (int i = x0; i <= x1; ++i) m = fminf(m, row[i]);
+    }
+  out[b] = m;
+}
+
 // ---------------------------------------------- ESDF from an occupancy grid --
 // Exact squared Euclidean distance transform by separable passes: after the
 // pass along x, y and z, f(v) = min over marked voxels w of |v - w|^2 (index
@@ -1416,9 +1511,21 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
   return hipGetLastError();
 }
 
+hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
+                         int cdz, float* out, hipStream_t s) {
+  const int n = cdx * cdy * cdz;
+  hipLaunchKernelGGL(k_coarse, dim3((n + 63) / 64), dim3(64), 0, s, vals, nx, ny, nz, shift, cdx,
+                     cdy, cdz, out);
+  return hipGetLastError();
+}
+
 int team_block(int W) { return (W > 1 ? W : WAVES_PER_BLOCK) * WAVE; }
+// dynamic LDS of an optimiser workgroup: a team's partial sums (double
+// buffered), history ring and coarse table; single wavefronts: one coarse
+// table each
 size_t team_lds(int W) {
-  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS) * sizeof(float) : 0;
+  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS + COARSE_MAX) * sizeof(float)
+               : (size_t)WAVES_PER_BLOCK * COARSE_MAX * sizeof(float);
 }
 
 using OptKernel = void (*)(const RobotDev*, const ParamsDev*, const ProbDev*, const TileDev*,

@@ -207,6 +207,7 @@ int admit(ds_plan* p, Serve* sv) {
       td[k].state = reinterpret_cast<float*>(p->arena.ptr(rec.state_off) + (size_t)k * ST_BYTES);
     }
     HIP_TRY(hipMemsetAsync(p->arena.ptr(rec.state_off), 0, (size_t)nt * ST_BYTES, sv->stream));
+    HIP_TRY(hipMemsetAsync(rec.seed_res, 0, (size_t)rec.S * sizeof(ds_seed_result), sv->stream));
     if (int rc = upload(p, sv->probs_dev + slot, &pd, sizeof pd, sv->stream)) return rc;
     if (int rc = upload(p, sv->tiles_dev + (size_t)slot * MAX_TILES_PER_REQ, td.data(),
                         td.size() * sizeof(TileDev), sv->stream))

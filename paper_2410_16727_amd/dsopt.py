@@ -60,7 +60,7 @@ class Params(C.Structure):
                 ("step_max", C.c_float), ("dt", C.c_float), ("tol_pos", C.c_float),
                 ("tol_rot", C.c_float), ("n_iters", C.c_int32), ("block_iters", C.c_int32),
                 ("waves_per_seed", C.c_int32), ("w_self", C.c_float),
-                ("swept_samples", C.c_int32)]
+                ("swept_samples", C.c_int32), ("exact_gathers", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -80,7 +80,7 @@ class SeedResult(C.Structure):
     _fields_ = [("cost", C.c_float), ("clearance", C.c_float), ("pos_err", C.c_float),
                 ("rot_err", C.c_float), ("max_jerk", C.c_float), ("collision_free", C.c_int32),
                 ("within_limits", C.c_int32), ("success", C.c_int32), ("valid", C.c_int32),
-                ("n_evals_cost", C.c_int32), ("n_evals_grad", C.c_int32), ("pad", C.c_int32)]
+                ("n_evals_cost", C.c_int32), ("n_evals_grad", C.c_int32), ("n_gathers", C.c_uint32)]
 
 
 class LatencyStats(C.Structure):
@@ -143,7 +143,7 @@ def check(rc):
 
 
 def _struct_dict(s):
-    return {k: getattr(s, k) for k, _ in s._fields_ if k != "pad"}
+    return {k: getattr(s, k) for k, _ in s._fields_}
 
 
 def robot_struct(robot):
@@ -184,6 +184,7 @@ def params_struct(p: dict, n_iters: int, block_iters: int = 10):
     s.waves_per_seed = int(p.get("waves_per_seed", 1))
     s.w_self = float(p.get("w_self", 0.0))
     s.swept_samples = int(p.get("swept_samples", 0))
+    s.exact_gathers = int(p.get("exact_gathers", 0))
     return s
 
 
