@@ -119,16 +119,21 @@ def run_single(args, dsopt, torch, configs, params):
     plan.kernel_timing(False)
     k_ms, k_n = plan.kernel_timing_read()
     ms_step = (t1 - t0) * 1e3 / args.steps
-    gather_bytes = float(np.sum(n_evals)) * T * robot.n_spheres * 32.0
+    # algorithmic bytes: 32 B per cell record the kernel gathered (its own
+    # per-seed counters); every sphere sample would be 32 B without the
+    # coarse-table skip
+    gather_bytes = float(np.sum(sres["n_gathers"])) * 32.0
+    sample_bytes = float(np.sum(n_evals)) * T * robot.n_spheres * 32.0
     avg_kernel_s = k_ms / max(k_n, 1) / 1e3
     achieved = gather_bytes / avg_kernel_s / 1e9
     log(f"[bench] {ms_step:.3f} ms/step, kernel {k_ms / max(k_n, 1):.3f} ms/launch, "
-        f"evals/seed {np.mean(n_evals):.1f}, gather {achieved:.1f} GB/s, best {best}")
+        f"evals/seed {np.mean(n_evals):.1f}, gathered {gather_bytes / sample_bytes:.3f} of "
+        f"the samples, {achieved:.1f} GB/s, best {best}")
     plan.close()
     return {
         "S": S, "T": T, "N": N, "spheres": robot.n_spheres, "grid": list(scene.dims),
         "ms_per_step": ms_step, "kernel_ms": k_ms / max(k_n, 1),
-        "gather_bytes": gather_bytes, "achieved_gbs": achieved,
+        "gather_bytes": gather_bytes, "sample_bytes": sample_bytes, "achieved_gbs": achieved,
         "evals_per_seed": float(np.mean(n_evals)), "best": best,
         "scene": scene, "robot": robot, "prob": prob,
     }
@@ -182,10 +187,11 @@ def run_batched(args, dsopt, torch, configs, params):
     base = tagc[0]
     tagc[0] += len(specs)
     plan.optimize([dict(s, tag=base + i) for i, s in enumerate(specs)])
-    gbytes = 0.0
+    gbytes = sbytes = 0.0
     for i, p in enumerate(probs):
         r = plan.seed_results(base + i, p.S)
-        gbytes += float(np.sum(evals_per_seed(r))) * p.T * robot.n_spheres * 32.0
+        gbytes += float(np.sum(r["n_gathers"])) * 32.0
+        sbytes += float(np.sum(evals_per_seed(r))) * p.T * robot.n_spheres * 32.0
         plan.release(base + i)
     out = {}
     for name, fn in [("batched", batched), ("plain", plain)]:
@@ -212,7 +218,8 @@ def run_batched(args, dsopt, torch, configs, params):
     out["roofline"] = {"bound": "hbm", "kernel": "k_optimize (one persistent launch)",
                        "achieved": gbytes / kb / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                        "frac": gbytes / kb / 1e9 / HBM_PEAK_GBS,
-                       "algorithmic_bytes_per_launch": gbytes}
+                       "algorithmic_bytes_per_launch": gbytes,
+                       "sample_bytes_per_launch": sbytes, "gathered_frac": gbytes / sbytes}
     out["speedup_batched_vs_plain"] = out["plain"]["ms_per_batch"] / out["batched"]["ms_per_batch"]
     out["workload"] = (f"batched-uneven: {len(probs)} problems, seeds U{{4..128}}, horizons "
                        f"U{{16..64}}, {sw} seed-waypoints, 128^3 ESDF per problem, {N} iters")
@@ -456,6 +463,8 @@ def main():
                      "frac": single["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
                      "kernel_ms": single["kernel_ms"],
                      "algorithmic_bytes_per_launch": single["gather_bytes"],
+                     "sample_bytes_per_launch": single["sample_bytes"],
+                     "gathered_frac": single["gather_bytes"] / single["sample_bytes"],
                      "evals_per_seed": single["evals_per_seed"]},
     }
     rec["esdf_from_occupancy"] = run_esdf_build(args, dsopt, torch, configs, params,
