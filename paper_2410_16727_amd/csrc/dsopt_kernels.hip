@@ -1430,23 +1430,35 @@ __global__ void k_esdf_pack(const float* __restrict__ v, int nx, int ny, int nz,
 }
 
 // Coarse table: minimum node value over each block of 2^shift cells per axis
-// (the nodes of the block's cells, inclusive of the far faces), one thread
-// per block.
-__global__ void k_coarse(const float* __restrict__ v, int nx, int ny, int nz, int shift, int cdx,
-                         int cdy, int cdz, float* __restrict__ out) {
-  const int b = blockIdx.x * blockDim.x + threadIdx.x;
-  if (b >= cdx * cdy * cdz) return;
+// (the nodes of the block's cells, inclusive of the far faces).  One
+// workgroup per block: its threads stride over the block's nodes (x runs
+// contiguous), then a shuffle and LDS minimum.
+constexpr int COARSE_THREADS = 256;
+
+__global__ void __launch_bounds__(COARSE_THREADS)
+k_coarse(const float* __restrict__ v, int nx, int ny, int nz, int shift, int cdx, int cdy,
+         float* __restrict__ out) {
+  __shared__ float s_min[COARSE_THREADS / WAVE];
+  const int b = blockIdx.x;
   const int bx = b % cdx, by = (b / cdx) % cdy, bz = b / (cdx * cdy);
   const int x0 = bx << shift, x1 = min((bx + 1) << shift, nx - 1);
   const int y0 = by << shift, y1 = min((by + 1) << shift, ny - 1);
   const int z0 = bz << shift, z1 = min((bz + 1) << shift, nz - 1);
+  const int lx = x1 - x0 + 1, ly = y1 - y0 + 1, lz = z1 - z0 + 1;
+  const int n = lx * ly * lz;
   float m = FLT_MAX;
-  for (int k = z0; k <= z1; ++k)
-    for (int j = y0; j <= y1; ++j) {
-      const float* row = v + (size_t)nx * (j + (size_t)ny * k);
-      for (int i = x0; i <= x1; ++i) m = fminf(m, row[i]);
-    }
-  out[b] = m;
+  for (int e = threadIdx.x; e < n; e += COARSE_THREADS) {
+    const int i = e % lx, j = (e / lx) % ly, k = e / (lx * ly);
+    m = fminf(m, v[(size_t)(x0 + i) + (size_t)nx * ((y0 + j) + (size_t)ny * (z0 + k))]);
+  }
+  for (int off = 1; off < WAVE; off <<= 1) m = fminf(m, __shfl_xor(m, off));
+  if ((threadIdx.x & (WAVE - 1)) == 0) s_min[threadIdx.x / WAVE] = m;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    float r = s_min[0];
+    for (int w = 1; w < COARSE_THREADS / WAVE; ++w) r = fminf(r, s_min[w]);
+    out[b] = r;
+  }
 }
 
 // ---------------------------------------------- ESDF from an occupancy grid --
@@ -1513,9 +1525,9 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
 
 hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
                          int cdz, float* out, hipStream_t s) {
-  const int n = cdx * cdy * cdz;
-  hipLaunchKernelGGL(k_coarse, dim3((n + 63) / 64), dim3(64), 0, s, vals, nx, ny, nz, shift, cdx,
-                     cdy, cdz, out);
+  (void)cdz;
+  hipLaunchKernelGGL(k_coarse, dim3(cdx * cdy * cdz), dim3(COARSE_THREADS), 0, s, vals, nx, ny,
+                     nz, shift, cdx, cdy, out);
   return hipGetLastError();
 }
 
