@@ -581,6 +581,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   const int LW = tm.W * L;
   EvalOut o;
   o.ng = 0;
+  o.perr = o.rerr = 0.f;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) o.g[j] = 0.f;
   float phisum = 0.f, clr = FLT_MAX;
@@ -634,6 +635,83 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     self_collision<MODE>(rb, P, q, cp, LW, selfsum, clr, o.g);
     coll += P.ws * selfsum;
   }
+  // goal pose, joint limits and smoothness: the same for every copy of the
+  // waypoint, so only the team's first wavefront computes them and only its
+  // first copy adds them to its share before the sums below
+  if (tm.w == 0) {
+    const bool first = lane < G;
+    float ge[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) ge[j] = 0.f;
+    // end effector and goal pose
+    const float* E = rb->Fee;
+    float Re[9], pe[3];
+#pragma unroll
+    for (int r = 0; r < 3; ++r) {
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        Re[3 * r + c] = R[3 * r] * E[c] + R[3 * r + 1] * E[4 + c] + R[3 * r + 2] * E[8 + c];
+      pe[r] = R[3 * r] * E[3] + R[3 * r + 1] * E[7] + R[3 * r + 2] * E[11] + p[r];
+    }
+    float ex = pe[0] - goal.pd[0], ey = pe[1] - goal.pd[1], ez = pe[2] - goal.pd[2];
+    float tr = 0.f;
+#pragma unroll
+    for (int k = 0; k < 9; ++k) tr += goal.Rd[k] * Re[k];
+    const bool last = (t == T - 1);
+    float goal_cost = P.wp * (ex * ex + ey * ey + ez * ez) + P.wr * (3.f - tr) * 0.25f;
+    if (GRAD && last) {
+      // force 2 w_p e at p_ee and torque -(w_r/4) w, w = vee(M - M^T), M = R_ee R_d^T
+      float M[9];
+#pragma unroll
+      for (int a = 0; a < 3; ++a)
+#pragma unroll
+        for (int b = 0; b < 3; ++b)
+          M[3 * a + b] = Re[3 * a] * goal.Rd[3 * b] + Re[3 * a + 1] * goal.Rd[3 * b + 1] +
+                         Re[3 * a + 2] * goal.Rd[3 * b + 2];
+      float wx = M[5] - M[7], wy = M[6] - M[2], wz = M[1] - M[3];
+      float k2 = 2.f * P.wp, k4 = -0.25f * P.wr;
+      float fx = k2 * ex, fy = k2 * ey, fz = k2 * ez;
+#pragma unroll
+      for (int i = 0; i < NJ; ++i) {
+        float zi[3], oi[3];
+        tw.get(i, zi, oi);
+        float rx = pe[0] - oi[0], ry = pe[1] - oi[1], rz = pe[2] - oi[2];
+        float tx = ry * fz - rz * fy + k4 * wx;
+        float ty = rz * fx - rx * fz + k4 * wy;
+        float tz = rx * fy - ry * fx + k4 * wz;
+        ge[i] += zi[0] * tx + zi[1] * ty + zi[2] * tz;
+      }
+    }
+    if (MODE == EV_RESULT) {
+      o.perr = sqrtf(ex * ex + ey * ey + ez * ez);
+      // angle of R_d^T R_ee: cos = (tr - 1) / 2, sin = |vee(R_ee R_d^T)| / 2
+      float M5, M7, M6, M2, M1, M3;
+      M5 = Re[3] * goal.Rd[6] + Re[4] * goal.Rd[7] + Re[5] * goal.Rd[8];
+      M7 = Re[6] * goal.Rd[3] + Re[7] * goal.Rd[4] + Re[8] * goal.Rd[5];
+      M6 = Re[6] * goal.Rd[0] + Re[7] * goal.Rd[1] + Re[8] * goal.Rd[2];
+      M2 = Re[0] * goal.Rd[6] + Re[1] * goal.Rd[7] + Re[2] * goal.Rd[8];
+      M1 = Re[0] * goal.Rd[3] + Re[1] * goal.Rd[4] + Re[2] * goal.Rd[5];
+      M3 = Re[3] * goal.Rd[0] + Re[4] * goal.Rd[1] + Re[5] * goal.Rd[2];
+      float wx = M5 - M7, wy = M6 - M2, wz = M1 - M3;
+      o.rerr = atan2f(0.5f * sqrtf(wx * wx + wy * wy + wz * wz), 0.5f * (tr - 1.f));
+    }
+    // joint limits
+    float lim = 0.f;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      float hi = q[j] - rb->qhi[j], lo = rb->qlo[j] - q[j];
+      float hp = fmaxf(hi, 0.f), lp = fmaxf(lo, 0.f);
+      lim += hp * hp + lp * lp;
+      if (GRAD) ge[j] += 2.f * P.wl * (hp - lp);
+    }
+    float sm = smoothness<GRAD>(P, q, t, T, ge);
+    const float extra = P.wl * lim + sm + (last ? goal_cost : 0.f);
+    coll += first ? extra : 0.f;
+    if (GRAD) {
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) o.g[j] += first ? ge[j] : 0.f;
+    }
+  }
   phisum = coll;
   // sum the shares of the L lanes of this waypoint (butterfly: every copy
   // ends with the same value)
@@ -672,71 +750,8 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     }
     tm.buf ^= 1;
   }
-  // end effector and goal pose
-  const float* E = rb->Fee;
-  float Re[9], pe[3];
-#pragma unroll
-  for (int r = 0; r < 3; ++r) {
-#pragma unroll
-    for (int c = 0; c < 3; ++c)
-      Re[3 * r + c] = R[3 * r] * E[c] + R[3 * r + 1] * E[4 + c] + R[3 * r + 2] * E[8 + c];
-    pe[r] = R[3 * r] * E[3] + R[3 * r + 1] * E[7] + R[3 * r + 2] * E[11] + p[r];
-  }
-  float ex = pe[0] - goal.pd[0], ey = pe[1] - goal.pd[1], ez = pe[2] - goal.pd[2];
-  float tr = 0.f;
-#pragma unroll
-  for (int k = 0; k < 9; ++k) tr += goal.Rd[k] * Re[k];
-  const bool last = (t == T - 1);
-  float goal_cost = P.wp * (ex * ex + ey * ey + ez * ez) + P.wr * (3.f - tr) * 0.25f;
-  if (GRAD && last) {
-    // force 2 w_p e at p_ee and torque -(w_r/4) w, w = vee(M - M^T), M = R_ee R_d^T
-    float M[9];
-#pragma unroll
-    for (int a = 0; a < 3; ++a)
-#pragma unroll
-      for (int b = 0; b < 3; ++b)
-        M[3 * a + b] = Re[3 * a] * goal.Rd[3 * b] + Re[3 * a + 1] * goal.Rd[3 * b + 1] +
-                       Re[3 * a + 2] * goal.Rd[3 * b + 2];
-    float wx = M[5] - M[7], wy = M[6] - M[2], wz = M[1] - M[3];
-    float k2 = 2.f * P.wp, k4 = -0.25f * P.wr;
-    float fx = k2 * ex, fy = k2 * ey, fz = k2 * ez;
-#pragma unroll
-    for (int i = 0; i < NJ; ++i) {
-      float zi[3], oi[3];
-      tw.get(i, zi, oi);
-      float rx = pe[0] - oi[0], ry = pe[1] - oi[1], rz = pe[2] - oi[2];
-      float tx = ry * fz - rz * fy + k4 * wx;
-      float ty = rz * fx - rx * fz + k4 * wy;
-      float tz = rx * fy - ry * fx + k4 * wz;
-      o.g[i] += zi[0] * tx + zi[1] * ty + zi[2] * tz;
-    }
-  }
-  if (MODE == EV_RESULT) {
-    o.perr = sqrtf(ex * ex + ey * ey + ez * ez);
-    // angle of R_d^T R_ee: cos = (tr - 1) / 2, sin = |vee(R_ee R_d^T)| / 2
-    float M5, M7, M6, M2, M1, M3;
-    M5 = Re[3] * goal.Rd[6] + Re[4] * goal.Rd[7] + Re[5] * goal.Rd[8];
-    M7 = Re[6] * goal.Rd[3] + Re[7] * goal.Rd[4] + Re[8] * goal.Rd[5];
-    M6 = Re[6] * goal.Rd[0] + Re[7] * goal.Rd[1] + Re[8] * goal.Rd[2];
-    M2 = Re[0] * goal.Rd[6] + Re[1] * goal.Rd[7] + Re[2] * goal.Rd[8];
-    M1 = Re[0] * goal.Rd[3] + Re[1] * goal.Rd[4] + Re[2] * goal.Rd[5];
-    M3 = Re[3] * goal.Rd[0] + Re[4] * goal.Rd[1] + Re[5] * goal.Rd[2];
-    float wx = M5 - M7, wy = M6 - M2, wz = M1 - M3;
-    o.rerr = atan2f(0.5f * sqrtf(wx * wx + wy * wy + wz * wz), 0.5f * (tr - 1.f));
-    o.clr = clr;
-  }
-  // joint limits
-  float lim = 0.f;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) {
-    float hi = q[j] - rb->qhi[j], lo = rb->qlo[j] - q[j];
-    float hp = fmaxf(hi, 0.f), lp = fmaxf(lo, 0.f);
-    lim += hp * hp + lp * lp;
-    if (GRAD) o.g[j] += 2.f * P.wl * (hp - lp);
-  }
-  float sm = smoothness<GRAD>(P, q, t, T, o.g);
-  float c = phisum + P.wl * lim + sm + (last ? goal_cost : 0.f);
-  o.cost = active ? c : 0.f;
+  if (MODE == EV_RESULT) o.clr = clr;
+  o.cost = active ? phisum : 0.f;
   if (GRAD) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) o.g[j] = (active && t > 0) ? o.g[j] : 0.f;
@@ -981,7 +996,7 @@ enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
 template <bool LDS_HIST, bool EXT>
 __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
                          const ProbDev* __restrict__ probs, const TileDev& td, int max_iters,
-                         Team& tm, float* hist_lds, float* coarse_lds) {
+                         Team& tm, float* hist_lds, float* coarse_lds, float* dir_lds) {
   TileCtx c;
   c.rb = rb;
   c.P = *pp;
@@ -1058,7 +1073,23 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
       trace_row(pb.tr_x, c, iter, x);
       trace_row(pb.tr_g, c, iter, g);
       trace_scalar(pb.tr_J, c, iter, J);
-      direction(c, hist, g, cnt, head, d);
+      if constexpr (LDS_HIST) {
+        // a team: the first wavefront runs the two-loop recursion, the team
+        // takes its direction (and history count) from LDS
+        DS_LDS float* dl = lds(dir_lds) + c.lane;
+        if (tm.w == 0) {
+          direction(c, hist, g, cnt, head, d);
+#pragma unroll
+          for (int j = 0; j < NJ; ++j) dl[j * WAVE] = d[j];
+          dl[NJ * WAVE] = __int_as_float(cnt);
+        }
+        tm.sync();
+#pragma unroll
+        for (int j = 0; j < NJ; ++j) d[j] = dl[j * WAVE];
+        cnt = __float_as_int(dl[NJ * WAVE]);
+      } else {
+        direction(c, hist, g, cnt, head, d);
+      }
       trace_row(pb.tr_d, c, iter, d);
       gtd = grp_sum(dot7(g, d), c.G);
 #pragma unroll
@@ -1225,11 +1256,12 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
     TileDev td = tiles[ti];
     if constexpr (TEAM) {
       run_tile<true, EXT>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE,
-                          s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS);
+                          s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS,
+                          s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS + COARSE_MAX);
       __syncthreads();   // the LDS ring is free for the next tile
     } else {
       run_tile<false, EXT>(rb, pp, probs, td, max_iters, tm, nullptr,
-                           s_dyn + (threadIdx.x / WAVE) * COARSE_MAX);
+                           s_dyn + (threadIdx.x / WAVE) * COARSE_MAX, nullptr);
     }
   }
 }
@@ -1533,10 +1565,11 @@ hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, i
 
 int team_block(int W) { return (W > 1 ? W : WAVES_PER_BLOCK) * WAVE; }
 // dynamic LDS of an optimiser workgroup: a team's partial sums (double
-// buffered), history ring and coarse table; single wavefronts: one coarse
-// table each
+// buffered), history ring, coarse table and direction broadcast; single
+// wavefronts: one coarse table each
 size_t team_lds(int W) {
-  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS + COARSE_MAX) * sizeof(float)
+  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS + COARSE_MAX + (NJ + 1) * WAVE) *
+                     sizeof(float)
                : (size_t)WAVES_PER_BLOCK * COARSE_MAX * sizeof(float);
 }
 
