@@ -174,6 +174,7 @@ void free_problem(ds_plan* p, ProblemRec& rec) {
   if (rec.launch) {
     if (--rec.launch->refs == 0) {
       if (rec.launch->tab_off != SIZE_MAX) p->arena.release(rec.launch->tab_off);
+      if (rec.launch->land_off != SIZE_MAX) p->land_pool.release(rec.launch->land_off);
       put_event(p, rec.launch->done);
     }
     rec.launch.reset();
@@ -208,16 +209,21 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   auto launch = std::make_shared<LaunchRec>();
   int total_tiles = 0;
   for (int i = 0; i < n; ++i) total_tiles += tiles_for(probs[i].n_seeds, probs[i].horizon);
-  size_t tab_bytes = ((size_t)n * sizeof(ProbDev) + 255) / 256 * 256 +
-                     ((size_t)total_tiles * sizeof(TileDev) + 255) / 256 * 256 + 256;
+  const size_t land_at = ((size_t)n * sizeof(ProbDev) + 255) / 256 * 256 +
+                         ((size_t)total_tiles * sizeof(TileDev) + 255) / 256 * 256 + 256;
+  size_t tab_bytes = land_at + (size_t)n * LAND_BYTES;
   launch->tab_off = arena_alloc(p, tab_bytes);
   if (launch->tab_off == SIZE_MAX) return fail(DS_ERR_NOMEM, "arena full (tables)");
+  // results land in pinned host memory when the pool has room (else
+  // ds_get_best copies them synchronously)
+  launch->land_off = p->land_pool.alloc((size_t)n * LAND_BYTES);
   auto cleanup = [&]() {
     for (auto& r : recs) {
       if (r.state_off != SIZE_MAX) p->arena.release(r.state_off);
       if (r.out_off != SIZE_MAX) p->arena.release(r.out_off);
     }
     p->arena.release(launch->tab_off);
+    if (launch->land_off != SIZE_MAX) p->land_pool.release(launch->land_off);
   };
   for (int i = 0; i < n; ++i) {
     const ds_problem& pr = probs[i];
@@ -235,13 +241,14 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
       cleanup();
       return rc;
     }
-    // per-seed gather counters accumulate over launches
-    HIP_TRY(hipMemsetAsync(rec.seed_res, 0, (size_t)rec.S * sizeof(ds_seed_result), s));
     pd[i] = make_probdev(p, pr);
     pd[i].final_traj = rec.final_traj;
     pd[i].seed_res = rec.seed_res;
     pd[i].result = rec.result;
     pd[i].best_traj = rec.best_traj;
+    pd[i].landing = p->arena.ptr(launch->tab_off) + land_at + (size_t)i * LAND_BYTES;
+    if (launch->land_off != SIZE_MAX)
+      rec.land = p->land_host + launch->land_off + (size_t)i * LAND_BYTES;
     if (n == 1) {
       pd[i].tr_x = tr_x; pd[i].tr_g = tr_g; pd[i].tr_J = tr_J; pd[i].tr_d = tr_d; pd[i].tr_a = tr_a;
     }
@@ -254,8 +261,6 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
       t.state = reinterpret_cast<float*>(p->arena.ptr(rec.state_off) + (size_t)k * ST_BYTES);
       td.push_back(t);
     }
-    // a fresh state: iteration counters start at zero
-    HIP_TRY(hipMemsetAsync(p->arena.ptr(rec.state_off), 0, (size_t)nt * ST_BYTES, s));
   }
   // longest tiles first: a tile's time grows with its group size (the
   // spheres each lane walks), and the persistent grid drains the table in
@@ -272,6 +277,8 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   if (int rc = upload(p, pd_dev, pd.data(), n * sizeof(ProbDev), s)) return rc;
   if (int rc = upload(p, td_dev, td.data(), td.size() * sizeof(TileDev), s)) return rc;
   HIP_TRY(launch_zero_i32(counter, 1, s));
+  // fresh tiles: iteration counters and seed results start at zero
+  HIP_TRY(launch_tile_reset(td_dev, pd_dev, total_tiles, s));
   const int W = p->params.waves;
   const int per_block = W > 1 ? 1 : WAVES_PER_BLOCK;
   int blocks = (total_tiles + per_block - 1) / per_block;
@@ -282,6 +289,9 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
       }))
     return rc;
   HIP_TRY(launch_best(pd_dev, n, nullptr, s));
+  if (launch->land_off != SIZE_MAX)
+    HIP_TRY(hipMemcpyAsync(p->land_host + launch->land_off, tab + land_at, (size_t)n * LAND_BYTES,
+                           hipMemcpyDeviceToHost, s));
   launch->done = get_event(p);
   if (!launch->done) return fail(DS_ERR_HIP, "event creation failed");
   HIP_TRY(hipEventRecord(launch->done, s));
@@ -385,6 +395,11 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   p->params_dev = reinterpret_cast<const ParamsDev*>(p->arena.ptr(p->params_off));
   HIP_TRY(hipMemcpy((void*)p->robot_dev, &rb, sizeof rb, hipMemcpyHostToDevice));
   HIP_TRY(hipMemcpy((void*)p->params_dev, &P, sizeof P, hipMemcpyHostToDevice));
+  {
+    const size_t land_cap = 4u << 20;
+    HIP_TRY(hipHostMalloc((void**)&p->land_host, land_cap, hipHostMallocDefault));
+    p->land_pool.init(p->land_host, land_cap);
+  }
   p->staging_cap = 8u << 20;
   HIP_TRY(hipHostMalloc((void**)&p->staging, p->staging_cap, hipHostMallocDefault));
   *out = p.release();
@@ -402,6 +417,7 @@ void ds_plan_destroy(ds_plan* p) {
   for (hipEvent_t e : p->staging_events) hipEventDestroy(e);
   for (hipEvent_t e : p->event_pool) hipEventDestroy(e);
   if (p->staging) hipHostFree(p->staging);
+  if (p->land_host) hipHostFree(p->land_host);
   delete p;
 }
 
@@ -541,6 +557,12 @@ int ds_get_best(ds_plan* p, int32_t tag, float* traj_host, ds_result* out) {
   if (it == p->problems.end()) return fail(DS_ERR_NOT_FOUND, "unknown problem tag %d", tag);
   ProblemRec& r = it->second;
   HIP_TRY(hipEventSynchronize(r.launch->done));
+  if (r.land) {   // landed with the launch
+    std::memcpy(out, r.land, sizeof(ds_result));
+    if (traj_host && out->best_seed >= 0)
+      std::memcpy(traj_host, r.land + 256, (size_t)r.T * NJ * sizeof(float));
+    return DS_OK;
+  }
   HIP_TRY(hipMemcpy(out, r.result, sizeof(ds_result), hipMemcpyDeviceToHost));
   if (traj_host && out->best_seed >= 0)
     HIP_TRY(hipMemcpy(traj_host, r.best_traj, (size_t)r.T * NJ * sizeof(float),

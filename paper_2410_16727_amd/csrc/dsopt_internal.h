@@ -66,7 +66,12 @@ struct ProbDev {
   ds_result* result;          // arena
   float* best_traj;           // arena [T][7], the best seed's trajectory
   float *tr_x, *tr_g, *tr_J, *tr_d, *tr_a;   // trace buffers or null
+  uint8_t* landing;           // null, or LAND_BYTES: result (256 B) then best trajectory
 };
+
+// a problem's result record and best trajectory, side by side, for one
+// copy to the host
+constexpr size_t LAND_BYTES = 256 + (size_t)DS_MAX_T * 7 * sizeof(float);
 
 struct TileDev {
   int32_t prob;          // index into the problem table
@@ -125,6 +130,8 @@ hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* 
 hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
                           hipStream_t s);
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
+hipError_t launch_tile_reset(const TileDev* tiles, const ProbDev* probs, int n_tiles,
+                             hipStream_t s);
 hipError_t launch_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz, float voxel,
                                       float* w0, float* w1, float* w2, float* w3, float* out,
                                       hipStream_t s);

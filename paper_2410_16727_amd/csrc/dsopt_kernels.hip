@@ -1292,9 +1292,13 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
   __syncthreads();
   const unsigned long long key = s_any ? s_key[1] : s_key[0];
   const int best = (key == ~0ull) ? -1 : (int)(key & 0xffffffffu);
+  float* land_traj = pb.landing ? reinterpret_cast<float*>(pb.landing + 256) : nullptr;
   if (best >= 0)
-    for (int e = threadIdx.x; e < pb.T * NJ; e += blockDim.x)
-      pb.best_traj[e] = pb.final_traj[(size_t)best * pb.T * NJ + e];
+    for (int e = threadIdx.x; e < pb.T * NJ; e += blockDim.x) {
+      const float v = pb.final_traj[(size_t)best * pb.T * NJ + e];
+      pb.best_traj[e] = v;
+      if (land_traj) land_traj[e] = v;
+    }
   if (threadIdx.x == 0) {
     ds_result out;
     out.best_seed = best;
@@ -1315,7 +1319,20 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
       out.pos_err_m = out.rot_err_rad = out.cost = out.min_clearance_m = out.max_jerk = NAN;
     }
     *pb.result = out;
+    if (pb.landing) *reinterpret_cast<ds_result*>(pb.landing) = out;
   }
+}
+
+// Fresh tiles: each tile's iteration counters (so the optimiser starts from
+// the seed) and its seed's result record (counters accumulate over
+// launches).  One workgroup of one wavefront per tile.
+__global__ void __launch_bounds__(64) k_tile_reset(const TileDev* __restrict__ tiles,
+                                                   const ProbDev* __restrict__ probs) {
+  const TileDev td = tiles[blockIdx.x];
+  reinterpret_cast<int*>(td.state)[ST_ITER + threadIdx.x] = 0;
+  constexpr int W = (int)(sizeof(ds_seed_result) / sizeof(int));
+  if (threadIdx.x < W)
+    reinterpret_cast<int*>(probs[td.prob].seed_res + td.seed0)[threadIdx.x] = 0;
 }
 
 // Objective (and gradient) of arbitrary trajectories: one wavefront per
@@ -1607,6 +1624,12 @@ int optimize_blocks_per_cu(int W, bool ext) {
                                                    team_lds(W)) != hipSuccess)
     return 1;
   return n > 0 ? n : 1;
+}
+
+hipError_t launch_tile_reset(const TileDev* tiles, const ProbDev* probs, int n_tiles,
+                             hipStream_t s) {
+  hipLaunchKernelGGL(k_tile_reset, dim3(n_tiles), dim3(64), 0, s, tiles, probs);
+  return hipGetLastError();
 }
 
 hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s) {

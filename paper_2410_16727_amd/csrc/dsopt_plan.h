@@ -98,7 +98,8 @@ struct SceneRec {
 // One launch of ds_optimize_seeds / traced: its tables live until every
 // problem in it is released.
 struct LaunchRec {
-  size_t tab_off = SIZE_MAX;   // ProbDev[n] + TileDev[nt] + counter
+  size_t tab_off = SIZE_MAX;   // ProbDev[n] + TileDev[nt] + counter + landing [n]
+  size_t land_off = SIZE_MAX;  // the launch's block in the plan's pinned landing pool
   hipEvent_t done = nullptr;
   int refs = 0;
 };
@@ -112,6 +113,7 @@ struct ProblemRec {
   ds_result* result = nullptr;
   float* best_traj = nullptr;
   float* final_traj = nullptr;
+  const uint8_t* land = nullptr;   // pinned copy of result + best trajectory, or null
   std::shared_ptr<LaunchRec> launch;
 };
 
@@ -133,6 +135,10 @@ struct ds_plan {
   // deferred arena frees, each guarded by an event
   std::vector<std::pair<hipEvent_t, size_t>> deferred;
   std::vector<hipEvent_t> event_pool;
+  // pinned landing pool: results of optimise launches arrive here with one
+  // asynchronous copy per launch
+  uint8_t* land_host = nullptr;
+  Arena land_pool;
   // pinned staging for table uploads
   uint8_t* staging = nullptr;
   size_t staging_cap = 0, staging_pos = 0;
