@@ -248,3 +248,44 @@ def test_autograd_matches_oracle_gradient():
             Y = Y - 1e-4 * Y.grad / Y.grad.abs().max()
     assert trajectory_cost(Y, plan, 0, prob.q_start, prob.goal).sum().item() < J0
     plan.close()
+
+
+def test_serving_with_optional_terms_matches_alone():
+    """The served loop with the variant kernels (swept sub-samples on):
+    every request's result equals its result optimised alone, bitwise."""
+    key = "A"
+    robot = configs.robot(key)
+    scene = configs.scenes(key, only={0})[0]
+    prob = configs.problems(key)[0]
+    plan = dsopt.Plan(robot, dict(P, waves_per_seed=8, swept_samples=2), 12, 256 << 20,
+                      block_iters=5)
+    plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
+    reqs = []
+    for r, (S, T) in enumerate([(3, 16), (5, 33), (2, 64), (4, 8)]):
+        reqs.append((S, T, torch.from_numpy(configs.seeds_for(key, 0, prob, S=S, T=T,
+                                                               stream=r)).cuda()))
+    alone = []
+    for r, (S, T, sd) in enumerate(reqs):
+        plan.optimize([{"scene": 0, "q_start": prob.q_start, "goal": prob.goal, "seeds": sd,
+                        "tag": 700 + r}])
+        alone.append(plan.get_best(700 + r, T))
+        plan.release(700 + r)
+    plan.serve_start(max_slots=3, queue_cap=16)
+    tickets = {r: plan.serve_submit({"scene": 0, "q_start": prob.q_start, "goal": prob.goal,
+                                     "seeds": sd}) for r, (S, T, sd) in enumerate(reqs)}
+    got = {}
+    for _ in range(2000):
+        plan.serve_step()
+        for r, t in tickets.items():
+            if r not in got:
+                res = plan.serve_poll(t, reqs[r][1])
+                if res is not None:
+                    got[r] = res
+        if len(got) == len(reqs):
+            break
+    assert len(got) == len(reqs)
+    for r in range(len(reqs)):
+        assert np.array_equal(got[r][0], alone[r][0]), r
+        assert got[r][1] == alone[r][1], r
+    plan.serve_stop()
+    plan.close()
