@@ -241,8 +241,8 @@ def run_serving(args, dsopt, torch, configs, params):
     N = w.iters
     cells = sum((s.dims[0] - 1) * (s.dims[1] - 1) * (s.dims[2] - 1) for s in scenes)
 
-    def make_plan(waves, block):
-        pl = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=waves), N,
+    def make_plan(waves, block, drain=0):
+        pl = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=waves, serve_drain=drain), N,
                         cells * 32 + (3 << 30), block_iters=block)
         for i, sc in enumerate(scenes):
             pl.upload_scene(i, sc.grid, sc.voxel, sc.origin)
@@ -316,7 +316,7 @@ def run_serving(args, dsopt, torch, configs, params):
             done_t[r] = tt
         return summarize(reqs, lat, done_t, name, warm)
 
-    sp = make_plan(args.serve_waves, args.serve_block)
+    sp = make_plan(args.serve_waves, args.serve_block, int(args.serve_drain))
     # plain serial form: on a plan with its own best (latency) team size
     pp = make_plan(args.serve_plain_waves, 10)
     out = {}
@@ -330,7 +330,8 @@ def run_serving(args, dsopt, torch, configs, params):
             "workload": (f"serving: Poisson {n} requests at {rate:g}/s ({warm} warm-up), "
                          f"seeds U{{8..128}}, horizons U{{32..64}}, 16 resident 200^3 ESDFs, "
                          f"{N} iters, blocks of {args.serve_block} iterations per graph replay, "
-                         f"{args.serve_slots} slots; served form {args.serve_waves} and plain "
+                         f"{args.serve_slots} slots{', run to completion when idle' if args.serve_drain else ''}; "
+                         f"served form {args.serve_waves} and plain "
                          f"serial form {args.serve_plain_waves} wavefronts per seed"),
             "served": served(sp, reqs, warm, f"served @{rate:g}/s"),
             "plain_serial": plain(pp, reqs, warm, f"plain serial @{rate:g}/s")}
@@ -415,6 +416,8 @@ def main():
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-block", type=int, default=25,
                     help="iterations per graph replay in the served form")
+    ap.add_argument("--serve-drain", action="store_true",
+                    help="served form: run the active requests to completion when none waits")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (this path has no multi-GPU form); got "

@@ -121,6 +121,11 @@ typedef struct ds_params {
                             its hinge and gradient are exactly zero, so results
                             are the same bit for bit.  1: gather every sample
                             (for verifying that equality). */
+  int32_t serve_drain;   /* 0 (default): every serving replay runs block_iters
+                            iterations of each active request.  1: when no request
+                            waits, a replay runs the active requests to completion
+                            (lower median latency at light load; a request that
+                            arrives meanwhile waits for that replay). */
 } ds_params;
 
 /* One planning problem (Sec. 3).  `seeds` are the seed trajectories
@@ -295,7 +300,7 @@ int ds_serve_start(ds_plan* plan, int max_slots, int queue_cap, void* stream);
 int ds_serve_submit(ds_plan* plan, const ds_problem* prob, uint64_t* ticket);
 /* Advance the loop by one step: collect completed replays, admit waiting
  * requests, enqueue one replay (block_iters iterations of every active
- * request).  Up to two replays are in flight; the call waits for the oldest
+ * request, or with serve_drain and nobody waiting, the rest of them).  Up to two replays are in flight; the call waits for the oldest
  * only when both are.  Returns the number of requests in the enqueued
  * replay (0: nothing to run) or an error. */
 int ds_serve_step(ds_plan* plan);

@@ -387,6 +387,7 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   // distances of metres; the margin keeps the zero-hinge proof exact
   P.far = prm->eps + 1e-5f;
   P.skip = prm->exact_gathers ? 0 : 1;
+  P.drain = prm->serve_drain ? 1 : 0;
   p->blocks_per_cu = optimize_blocks_per_cu(P.waves, params_ext(P));
 
   p->robot_off = p->arena.alloc(sizeof(RobotDev));

@@ -34,6 +34,7 @@ struct ParamsDev {
   int32_t nsub;          // swept sub-samples per segment
   float far;             // a block minimum >= radius + far proves a zero hinge
   int32_t skip;          // use the coarse table (0: gather every sample)
+  int32_t drain;         // serving: run to completion when nobody waits
 };
 
 // One resident scene: the 8 corners of cell (i,j,k) are the 32-byte record
@@ -137,8 +138,8 @@ hipError_t launch_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz
                                       hipStream_t s);
 hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                              const TileDev* tiles, const int* tile_list, int* counter,
-                             int max_tiles, int grid_blocks, int max_iters, int waves, bool ext,
-                             hipStream_t s);
+                             int max_tiles, int grid_blocks, const int* max_iters_dev, int waves,
+                             bool ext, hipStream_t s);
 int team_block(int waves);
 int optimize_blocks_per_cu(int waves, bool ext);
 }  // namespace dsk

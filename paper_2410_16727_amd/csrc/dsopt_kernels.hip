@@ -1226,12 +1226,13 @@ __global__ void __launch_bounds__(MAX_TEAM * WAVE)
 k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
            const ProbDev* __restrict__ probs, const TileDev* __restrict__ tiles,
            const int* __restrict__ tile_list, const int* __restrict__ n_tiles_dev, int n_tiles,
-           int* counter, int max_iters) {
+           int* counter, int max_iters, const int* __restrict__ max_iters_dev) {
   extern __shared__ float s_dyn[];
   __shared__ int s_tile;
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
   const int nt = n_tiles_dev ? *n_tiles_dev : n_tiles;
+  if (max_iters_dev) max_iters = *max_iters_dev;   // serving: set per replay
   Team tm;
   tm.W = TEAM ? pp->waves : 1;
   tm.w = TEAM ? (int)(threadIdx.x / WAVE) : 0;
@@ -1591,7 +1592,7 @@ size_t team_lds(int W) {
 }
 
 using OptKernel = void (*)(const RobotDev*, const ParamsDev*, const ProbDev*, const TileDev*,
-                           const int*, const int*, int, int*, int);
+                           const int*, const int*, int, int*, int, const int*);
 
 static OptKernel optimize_kernel(int W, bool ext) {
   if (W > 1) return ext ? k_optimize<true, true> : k_optimize<true, false>;
@@ -1603,18 +1604,19 @@ hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDe
                            int max_iters, int W, bool ext, hipStream_t s) {
   hipLaunchKernelGGL(optimize_kernel(W, ext), dim3(grid_blocks), dim3(team_block(W)),
                      team_lds(W), s, rb, pp, probs, tiles, (const int*)nullptr,
-                     (const int*)nullptr, n_tiles, counter, max_iters);
+                     (const int*)nullptr, n_tiles, counter, max_iters, (const int*)nullptr);
   return hipGetLastError();
 }
 
 hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                              const TileDev* tiles, const int* tile_list, int* counter,
-                             int max_tiles, int grid_blocks, int max_iters, int W, bool ext,
-                             hipStream_t s) {
-  // tile_list[0] holds the number of listed tiles, the indices follow
+                             int max_tiles, int grid_blocks, const int* max_iters_dev, int W,
+                             bool ext, hipStream_t s) {
+  // tile_list[0] holds the number of listed tiles, the indices follow; the
+  // iterations of this replay are read from max_iters_dev
   hipLaunchKernelGGL(optimize_kernel(W, ext), dim3(grid_blocks), dim3(team_block(W)),
                      team_lds(W), s, rb, pp, probs, tiles, tile_list + 1, tile_list, max_tiles,
-                     counter, max_iters);
+                     counter, 0, max_iters_dev);
   return hipGetLastError();
 }
 

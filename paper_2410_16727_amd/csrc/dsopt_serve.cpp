@@ -65,7 +65,7 @@ struct ServeReq {
   ds_problem prob;
   double t_submit = 0, t_done = 0;
   int slot = -1;
-  int blocks_left = 0;
+  int iters_left = 0;       // iterations not yet enqueued
   bool done = false;
   ds_result result{};
   std::vector<float> best;
@@ -88,10 +88,12 @@ struct Serve {
   size_t tab_off = SIZE_MAX;
   ProbDev* probs_dev = nullptr;
   TileDev* tiles_dev = nullptr;
-  int* slot_list_dev = nullptr;   // [0] = count, then slot indices
+  int* slot_list_dev = nullptr;   // [0] = count, then slot indices; [max_slots + 1] =
+                                  // iterations of the replay
   int* tile_list_dev = nullptr;   // [0] = count, then tile indices (follows the slot list)
   size_t slot_list_bytes = 0;     // padded size of the slot list region
   bool lists_dirty = true;        // membership changed since the last upload
+  int block = -1;                 // iterations of the last uploaded replay
   int* counter_dev = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
@@ -221,8 +223,7 @@ int admit(ds_plan* p, Serve* sv) {
     sl.ntiles = nt;
     r.slot = slot;
     sv->lists_dirty = true;
-    int B = std::max(1, p->params.block_iters);
-    r.blocks_left = std::max(1, (p->params.n_iters + B - 1) / B);
+    r.iters_left = p->params.n_iters;
     sv->queue.pop_front();
   }
   return DS_OK;
@@ -254,7 +255,7 @@ int ds_serve_start(ds_plan* p, int max_slots, int queue_cap, void* stream) {
   size_t a = ((size_t)max_slots * sizeof(ProbDev) + 255) / 256 * 256;
   size_t b = (max_tiles * sizeof(TileDev) + 255) / 256 * 256;
   size_t c = ((max_tiles + 1) * sizeof(int) + 255) / 256 * 256;
-  size_t d = (((size_t)max_slots + 1) * sizeof(int) + 255) / 256 * 256;
+  size_t d = (((size_t)max_slots + 2) * sizeof(int) + 255) / 256 * 256;
   sv->tab_off = arena_alloc(p, a + b + c + d + 256);
   if (sv->tab_off == SIZE_MAX) {
     ds_serve_free(p);
@@ -282,7 +283,7 @@ int ds_serve_start(ds_plan* p, int max_slots, int queue_cap, void* stream) {
   hipError_t e1 = launch_zero_i32(sv->counter_dev, 1, sv->stream);
   hipError_t e2 = launch_serve_step(p->robot_dev, p->params_dev, sv->probs_dev, sv->tiles_dev,
                                     sv->tile_list_dev, sv->counter_dev, (int)max_tiles, grid,
-                                    p->params.block_iters, p->params.waves,
+                                    sv->slot_list_dev + max_slots + 1, p->params.waves,
                                     params_ext(p->params), sv->stream);
   hipError_t e3 = launch_best(sv->probs_dev, max_slots, sv->slot_list_dev, sv->stream);
   hipError_t e4 = hipStreamEndCapture(sv->stream, &sv->graph);
@@ -330,12 +331,21 @@ int ds_serve_step(ds_plan* p) {
   int active = (int)sv->host_slots.size() - 1;
   if (active == 0) return 0;
   sv->host_slots[0] = active;
+  // iterations of this replay: block_iters; with serve_drain and nobody
+  // waiting, the active requests run to completion in one replay
+  int block = std::max(1, p->params.block_iters);
+  if (p->params.drain && sv->queue.empty()) {
+    for (int i = 1; i <= active; ++i)
+      block = std::max(block, sv->reqs[sv->slots[sv->host_slots[i]].ticket].iters_left);
+  }
+  if (block != sv->block) sv->lists_dirty = true;
   if (sv->lists_dirty) {
     // slot list, then the tile list at its fixed offset: one upload, only
     // when the membership changed
     const size_t ns = sv->slot_list_bytes / sizeof(int);
     sv->host_lists.assign(ns + 1, 0);
     std::copy(sv->host_slots.begin(), sv->host_slots.end(), sv->host_lists.begin());
+    sv->host_lists[sv->max_slots + 1] = block;
     for (int i = 1; i <= active; ++i) {
       const int slot = sv->host_slots[i];
       for (int k = 0; k < sv->slots[slot].ntiles; ++k)
@@ -346,6 +356,7 @@ int ds_serve_step(ds_plan* p) {
                         sv->host_lists.size() * sizeof(int), sv->stream))
       return rc;
     sv->lists_dirty = false;
+    sv->block = block;
   }
   if (int rc = timed_launch(p, sv->stream, [&]() { return hipGraphLaunch(sv->exec, sv->stream); }))
     return rc;
@@ -356,7 +367,8 @@ int ds_serve_step(ds_plan* p) {
     const int slot = sv->host_slots[i];
     Slot& sl = sv->slots[slot];
     ServeReq& r = sv->reqs[sl.ticket];
-    if (--r.blocks_left > 0) continue;
+    r.iters_left -= block;
+    if (r.iters_left > 0) continue;
     // last block of this request: land its result behind the replay, free
     // the slot, release its memory once the copies are done
     HIP_TRY(hipMemcpyAsync(&set[slot], sl.result,

@@ -60,7 +60,8 @@ class Params(C.Structure):
                 ("step_max", C.c_float), ("dt", C.c_float), ("tol_pos", C.c_float),
                 ("tol_rot", C.c_float), ("n_iters", C.c_int32), ("block_iters", C.c_int32),
                 ("waves_per_seed", C.c_int32), ("w_self", C.c_float),
-                ("swept_samples", C.c_int32), ("exact_gathers", C.c_int32)]
+                ("swept_samples", C.c_int32), ("exact_gathers", C.c_int32),
+                ("serve_drain", C.c_int32)]
 
 
 class Problem(C.Structure):
@@ -185,6 +186,7 @@ def params_struct(p: dict, n_iters: int, block_iters: int = 10):
     s.w_self = float(p.get("w_self", 0.0))
     s.swept_samples = int(p.get("swept_samples", 0))
     s.exact_gathers = int(p.get("exact_gathers", 0))
+    s.serve_drain = int(p.get("serve_drain", 0))
     return s
 
 

@@ -289,3 +289,42 @@ def test_serving_with_optional_terms_matches_alone():
         assert got[r][1] == alone[r][1], r
     plan.serve_stop()
     plan.close()
+
+
+def test_serving_drain_when_idle_matches_alone():
+    """serve_drain: with nobody waiting a replay runs the active requests to
+    completion; results stay bitwise those of the requests alone, and a
+    lone request needs a single replay."""
+    key = "A"
+    robot = configs.robot(key)
+    scene = configs.scenes(key, only={0})[0]
+    prob = configs.problems(key)[0]
+    plan = dsopt.Plan(robot, dict(P, serve_drain=1), 20, 256 << 20, block_iters=4)
+    plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
+    reqs = [(S, T, torch.from_numpy(configs.seeds_for(key, 0, prob, S=S, T=T, stream=r)).cuda())
+            for r, (S, T) in enumerate([(4, 32), (7, 20), (2, 64)])]
+    alone = []
+    for r, (S, T, sd) in enumerate(reqs):
+        plan.optimize([{"scene": 0, "q_start": prob.q_start, "goal": prob.goal, "seeds": sd,
+                        "tag": 800 + r}])
+        alone.append(plan.get_best(800 + r, T))
+        plan.release(800 + r)
+    plan.serve_start(max_slots=4, queue_cap=8)
+    got = {}
+    for r, (S, T, sd) in enumerate(reqs):      # one at a time: one replay each
+        t = plan.serve_submit({"scene": 0, "q_start": prob.q_start, "goal": prob.goal,
+                               "seeds": sd})
+        for _ in range(1000):
+            plan.serve_step()
+            res = plan.serve_poll(t, T)
+            if res is not None:
+                got[r] = res
+                break
+    st = plan.serve_stats()
+    assert st["completed"] == len(reqs)
+    assert st["steps"] == len(reqs)
+    for r in range(len(reqs)):
+        assert np.array_equal(got[r][0], alone[r][0]), r
+        assert got[r][1] == alone[r][1], r
+    plan.serve_stop()
+    plan.close()
