@@ -636,9 +636,12 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     coll += P.ws * selfsum;
   }
   // goal pose, joint limits and smoothness: the same for every copy of the
-  // waypoint, so only the team's first wavefront computes them and only its
-  // first copy adds them to its share before the sums below
-  if (tm.w == 0) {
+  // waypoint, so one wavefront of the team computes them and only its first
+  // copy adds them to its share before the sums below -- the second
+  // wavefront (off the first one's path, which also runs the direction),
+  // except in the result pass, whose goal errors the first one writes
+  const int xw = (MODE == EV_RESULT || tm.W == 1) ? 0 : 1;
+  if (tm.w == xw) {
     const bool first = lane < G;
     float ge[NJ];
 #pragma unroll
