@@ -341,6 +341,56 @@ def run_serving(args, dsopt, torch, configs, params):
     return out
 
 
+def run_differentiation(args, dsopt, torch, configs, params):
+    """Cost + gradient of 256 seeds x 64 waypoints (60 spheres, 200^3) in
+    one call, and the same through the autograd function (forward cost,
+    backward adjoint with kinematics recomputed), timed with events on the
+    stream both run on."""
+    from paper_2410_16727_amd.autograd import trajectory_cost
+    key = "C"
+    robot = configs.robot(key)
+    scene = configs.scenes(key, only={0})[0]
+    prob = configs.problems(key)[0]
+    cells = (scene.dims[0] - 1) * (scene.dims[1] - 1) * (scene.dims[2] - 1)
+    plan = dsopt.Plan(robot, params.DEFAULT, 1, cells * 32 + (1 << 30))
+    plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
+    X = torch.from_numpy(configs.seeds_for(key, 0, prob)).cuda()
+    S, T = X.shape[0], X.shape[1]
+    reps = 50
+
+    def timed(fn):
+        for _ in range(3):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    ms_cg = timed(lambda: plan.cost_grad(0, prob.q_start, prob.goal, X))
+
+    def fwd_bwd():
+        Xr = X.clone().requires_grad_(True)
+        trajectory_cost(Xr, plan, 0, prob.q_start, prob.goal).sum().backward()
+
+    ms_ag = timed(fwd_bwd)
+    plan.close()
+    sample_bytes = float(S * T * robot.n_spheres * 32)
+    achieved = sample_bytes / (ms_cg * 1e-3) / 1e9
+    log(f"[bench] differentiation: cost+grad {ms_cg:.3f} ms ({S * T / (ms_cg * 1e-3):.3e} "
+        f"seed-waypoint evals/s), autograd forward+backward {ms_ag:.3f} ms")
+    return {"workload": f"differentiation: {S} seeds x {T} waypoints, {robot.n_spheres} spheres, "
+                        f"{scene.dims[0]}^3 ESDF, one cost+gradient call",
+            "cost_grad_ms": ms_cg, "seed_waypoint_evals_per_s": S * T / (ms_cg * 1e-3),
+            "autograd_fwd_bwd_ms": ms_ag,
+            "roofline": {"bound": "hbm", "kernel": "k_cost (cost+gradient)", "achieved": achieved,
+                         "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                         "algorithmic_bytes_per_launch": sample_bytes}}
+
+
 def run_esdf_build(args, dsopt, torch, configs, params, scene):
     """Distance field of the cluttered scene built on the GPU from its
     occupancy grid (exact signed EDT), timed with events."""
@@ -472,6 +522,7 @@ def main():
     }
     rec["esdf_from_occupancy"] = run_esdf_build(args, dsopt, torch, configs, params,
                                                 single["scene"])
+    rec["differentiation"] = run_differentiation(args, dsopt, torch, configs, params)
     if not args.no_batched:
         rec["batched"] = run_batched(args, dsopt, torch, configs, params)
     if not args.no_serving:
