@@ -609,7 +609,7 @@ static int cost_common(ds_plan* p, const ds_problem* prob, const float* X, int S
   ProbDev* dev = reinterpret_cast<ProbDev*>(p->arena.ptr(off));
   if (int rc = upload(p, dev, &pd, sizeof pd, s)) return rc;
   HIP_TRY(launch_cost(p->robot_dev, p->params_dev, dev, X, S, T, dJ, J_out, dX, with_grad,
-                      params_ext(p->params), s));
+                      params_ext(p->params), p->cu_count, s));
   return defer_free(p, off, s);
 }
 
@@ -639,7 +639,7 @@ int ds_guide(ds_plan* p, const ds_problem* prob, float* X, int S, int T, float a
   ProbDev* dev = reinterpret_cast<ProbDev*>(p->arena.ptr(off));
   if (int rc = upload(p, dev, &pd, sizeof pd, s)) return rc;
   HIP_TRY(launch_guide(p->robot_dev, p->params_dev, dev, X, S, T, alpha, n_steps, J_out,
-                       params_ext(p->params), s));
+                       params_ext(p->params), p->cu_count, s));
   return defer_free(p, off, s);
 }
 

@@ -124,10 +124,10 @@ hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDe
 hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s);
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
-                       int with_grad, bool ext, hipStream_t s);
+                       int with_grad, bool ext, int cu_count, hipStream_t s);
 hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob, float* X,
                         int S, int T, float alpha, int n_steps, float* J_out, bool ext,
-                        hipStream_t s);
+                        int cu_count, hipStream_t s);
 hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
                           hipStream_t s);
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);

@@ -1339,32 +1339,46 @@ __global__ void __launch_bounds__(64) k_tile_reset(const TileDev* __restrict__ t
     reinterpret_cast<int*>(probs[td.prob].seed_res + td.seed0)[threadIdx.x] = 0;
 }
 
-// Objective (and gradient) of arbitrary trajectories: one wavefront per
-// seed group of G lanes (G = smallest of 16/32/64 holding T).
+// Seed of this wavefront in k_cost / k_guide: W = 1, one seed per
+// wavefront (WAVES_PER_BLOCK per workgroup); W > 1, one seed per workgroup
+// of W wavefronts (a team, for batches too small to fill the chip).
+__device__ __forceinline__ int seed_of(int W, float* team_lds, Team& tm) {
+  tm.buf = 0;
+  if (W > 1) {
+    tm.W = W;
+    tm.w = threadIdx.x / WAVE;
+    tm.lds = team_lds;
+    return blockIdx.x;
+  }
+  tm.W = 1;
+  tm.w = 0;
+  tm.lds = nullptr;
+  return (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
+}
+
+// Objective (and gradient) of arbitrary trajectories: one wavefront (or a
+// team) per seed group of G lanes (G = smallest of 16/32/64 holding T).
 template <bool EXT>
 __global__ void __launch_bounds__(BLOCK)
 k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const ProbDev* __restrict__ pb, const float* __restrict__ X, int S, int T, int G,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
-       int with_grad) {
+       int with_grad, int W) {
+  extern __shared__ float s_team[];
   __shared__ float s_cm[COARSE_MAX];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
-  const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
-  if (seed >= S) return;   // whole wavefront past the end
+  Team tm;
+  const int seed = seed_of(W, s_team, tm);
+  if (seed >= S) return;   // whole wavefront (team: whole workgroup) past the end
   const int t = lane & (G - 1);
-  const bool owner = lane < G;
+  const bool owner = tm.w == 0 && lane < G;
   const bool active = t < T;
   ParamsDev P = *pp;
   Sampler Sm = make_sampler(pb->sc);
   Sm.cm = lds(s_cm);
   Goal goal = make_goal(*pb);
-  Team tm;
-  tm.W = 1;
-  tm.w = 0;
-  tm.lds = nullptr;
-  tm.buf = 0;
   float x[NJ];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) x[j] = active ? X[((size_t)seed * T + t) * NJ + j] : 0.f;
@@ -1381,34 +1395,31 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
     EvalOut e = eval_any<EV_COST, EXT>(use_pipe(rb, tm, G), rb, P, Sm, goal, x, t, T, G, active, tm);
     J = grp_sum(e.cost, G);
   }
-  if (J_out && lane == 0) J_out[seed] = J;
+  if (J_out && tm.w == 0 && lane == 0) J_out[seed] = J;
 }
 
 // Guidance: n gradient steps x <- x - alpha * g on every trajectory, one
-// wavefront per seed (same evaluation as the optimiser).
+// wavefront (or a team) per seed (same evaluation as the optimiser).
 template <bool EXT>
 __global__ void __launch_bounds__(BLOCK)
 k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
-        int n_steps, float* __restrict__ J_out) {
+        int n_steps, float* __restrict__ J_out, int W) {
+  extern __shared__ float s_team[];
   __shared__ float s_cm[COARSE_MAX];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
-  const int seed = (blockIdx.x * BLOCK + threadIdx.x) / WAVE;
-  if (seed >= S) return;   // whole wavefront past the end
+  Team tm;
+  const int seed = seed_of(W, s_team, tm);
+  if (seed >= S) return;   // whole wavefront (team: whole workgroup) past the end
   const int t = lane & (G - 1);
-  const bool owner = lane < G;
+  const bool owner = tm.w == 0 && lane < G;
   const bool active = t < T;
   ParamsDev P = *pp;
   Sampler Sm = make_sampler(pb->sc);
   Sm.cm = lds(s_cm);
   Goal goal = make_goal(*pb);
-  Team tm;
-  tm.W = 1;
-  tm.w = 0;
-  tm.lds = nullptr;
-  tm.buf = 0;
   const bool pipe = use_pipe(rb, tm, G);
   float x[NJ];
 #pragma unroll
@@ -1421,7 +1432,7 @@ k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   if (J_out) {
     EvalOut e = eval_any<EV_COST, EXT>(pipe, rb, P, Sm, goal, x, t, T, G, active, tm);
     float J = grp_sum(e.cost, G);
-    if (lane == 0) J_out[seed] = J;
+    if (tm.w == 0 && lane == 0) J_out[seed] = J;
   }
   if (active && owner) {
 #pragma unroll
@@ -1642,23 +1653,36 @@ hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipSt
   return hipGetLastError();
 }
 
+// Team size for k_cost / k_guide: one wavefront per seed when the seeds
+// give at least WAVES_PER_BLOCK wavefronts per CU, else teams of up to
+// WAVES_PER_BLOCK wavefronts per seed.
+static int cost_team(int S, int cu_count) {
+  int W = 1;
+  while (W < WAVES_PER_BLOCK && (long long)S * W < (long long)WAVES_PER_BLOCK * cu_count) W *= 2;
+  return W;
+}
+
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
-                       int with_grad, bool ext, hipStream_t s) {
-  int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
-  int blocks = (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  hipLaunchKernelGGL(ext ? k_cost<true> : k_cost<false>, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, dJ,
-                     J_out, dX, with_grad);
+                       int with_grad, bool ext, int cu_count, hipStream_t s) {
+  const int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
+  const int W = cost_team(S, cu_count);
+  const int blocks = W > 1 ? S : (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  const size_t lds_bytes = W > 1 ? (size_t)2 * W * PART * WAVE * sizeof(float) : 0;
+  hipLaunchKernelGGL(ext ? k_cost<true> : k_cost<false>, dim3(blocks), dim3(W > 1 ? W * WAVE : BLOCK),
+                     lds_bytes, s, rb, pp, prob, X, S, T, G, dJ, J_out, dX, with_grad, W);
   return hipGetLastError();
 }
 
 hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob, float* X,
                         int S, int T, float alpha, int n_steps, float* J_out, bool ext,
-                        hipStream_t s) {
-  int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
-  int blocks = (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
-  hipLaunchKernelGGL(ext ? k_guide<true> : k_guide<false>, dim3(blocks), dim3(BLOCK), 0, s, rb, pp, prob, X, S, T, G, alpha,
-                     n_steps, J_out);
+                        int cu_count, hipStream_t s) {
+  const int G = T <= 16 ? 16 : (T <= 32 ? 32 : 64);
+  const int W = cost_team(S, cu_count);
+  const int blocks = W > 1 ? S : (S + WAVES_PER_BLOCK - 1) / WAVES_PER_BLOCK;
+  const size_t lds_bytes = W > 1 ? (size_t)2 * W * PART * WAVE * sizeof(float) : 0;
+  hipLaunchKernelGGL(ext ? k_guide<true> : k_guide<false>, dim3(blocks), dim3(W > 1 ? W * WAVE : BLOCK),
+                     lds_bytes, s, rb, pp, prob, X, S, T, G, alpha, n_steps, J_out, W);
   return hipGetLastError();
 }
 
