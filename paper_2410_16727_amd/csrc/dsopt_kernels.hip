@@ -1540,11 +1540,15 @@ __global__ void k_edt_init(const uint8_t* __restrict__ occ, long long n, int tar
 }
 
 // One pass along `axis` (0 = x, 1 = y, 2 = z): one workgroup per line, the
-// line staged in LDS, every element scans the whole line.
+// line staged in LDS.  Element p takes min_q (p - q)^2 + f(q) by scanning
+// outward from q = p and stopping once r^2 >= the best value so far (every
+// farther term is at least r^2): the same minimum as a scan of the whole
+// line.  A line with no finite value stays at "none".
 __global__ void __launch_bounds__(256)
 k_edt_pass(const float* __restrict__ fin, float* __restrict__ fout, int nx, int ny, int nz,
            int axis) {
   extern __shared__ float line[];
+  __shared__ int s_any;
   const int n = axis == 0 ? nx : (axis == 1 ? ny : nz);
   const long long stride = axis == 0 ? 1 : (axis == 1 ? (long long)nx : (long long)nx * ny);
   // the line's first element
@@ -1552,13 +1556,26 @@ k_edt_pass(const float* __restrict__ fin, float* __restrict__ fout, int nx, int 
   if (axis == 0) base = l * nx;
   else if (axis == 1) base = (l / nx) * (long long)nx * ny + (l % nx);
   else base = l;
-  for (int q = threadIdx.x; q < n; q += blockDim.x) line[q] = fin[base + q * stride];
+  if (threadIdx.x == 0) s_any = 0;
   __syncthreads();
+  int any = 0;
+  for (int q = threadIdx.x; q < n; q += blockDim.x) {
+    const float v = fin[base + q * stride];
+    line[q] = v;
+    any |= v < EDT_NONE;
+  }
+  if (any) s_any = 1;
+  __syncthreads();
+  const bool finite = s_any != 0;
   for (int pidx = threadIdx.x; pidx < n; pidx += blockDim.x) {
-    float best = EDT_NONE;
-    for (int q = 0; q < n; ++q) {
-      float dq = (float)(pidx - q);
-      best = fminf(best, dq * dq + line[q]);
+    float best = line[pidx];
+    if (finite) {
+      for (int r = 1; r < n; ++r) {
+        const float r2 = (float)(r * r);
+        if (r2 >= best) break;
+        if (pidx - r >= 0) best = fminf(best, r2 + line[pidx - r]);
+        if (pidx + r < n) best = fminf(best, r2 + line[pidx + r]);
+      }
     }
     fout[base + pidx * stride] = best;
   }
