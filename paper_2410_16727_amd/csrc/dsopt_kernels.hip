@@ -55,9 +55,10 @@ constexpr int CH = DSOPT_CH;                     // sphere gathers in flight per
 // Butterfly reductions over a lane group of G = 16, 32 or 64 lanes.  The
 // first four stages pair lanes inside a 16-lane row with DPP (quad
 // permutations 1<->0 / 2<->0, then the half-row and row mirrors), the
-// remaining ones with cross-row shuffles.  Every pairing is an involution,
-// so both partners add the same two numbers and every lane of the group ends
-// with bitwise the same result.
+// remaining ones exchange rows (lane ^ 16) and halves (lane ^ 32) with the
+// permlane swaps -- VALU instructions, no LDS round trip.  Every pairing is
+// an involution, so both partners add the same two numbers and every lane of
+// the group ends with bitwise the same result.
 constexpr int DPP_QUAD_XOR1 = 0xB1;   // quad_perm [1,0,3,2]
 constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int DPP_HALF_MIRROR = 0x141;
@@ -67,6 +68,24 @@ template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(
       __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// The value of lane ^ 16 (v_permlane16_swap exchanges the odd rows of its
+// first operand with the even rows of its second: with both operands v, an
+// even row finds its partner row in the second result, an odd row in the
+// first) and of lane ^ 32 (v_permlane32_swap: the upper half of the first
+// operand with the lower half of the second).
+__device__ __forceinline__ unsigned xor16_bits(unsigned v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(v, v, true, false);
+  return (threadIdx.x & 16) ? r[0] : r[1];
+}
+__device__ __forceinline__ unsigned xor32_bits(unsigned v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(v, v, true, false);
+  return (threadIdx.x & 32) ? r[0] : r[1];
+}
+__device__ __forceinline__ float lane_xor(float v, int off) {
+  return __uint_as_float(off == 16 ? xor16_bits(__float_as_uint(v))
+                                   : xor32_bits(__float_as_uint(v)));
 }
 
 struct OpSum { __device__ static float f(float a, float b) { return a + b; } };
@@ -79,8 +98,19 @@ __device__ __forceinline__ float grp_reduce(float v, int G) {
   v = Op::f(v, dpp<DPP_QUAD_XOR2>(v));
   v = Op::f(v, dpp<DPP_HALF_MIRROR>(v));
   v = Op::f(v, dpp<DPP_MIRROR>(v));
-  for (int off = 16; off < G; off <<= 1) v = Op::f(v, __shfl_xor(v, off));
+  if (G > 16) v = Op::f(v, lane_xor(v, 16));
+  if (G > 32) v = Op::f(v, lane_xor(v, 32));
   return v;
+}
+
+// Maximum of an int over the whole wavefront (every lane gets it).
+__device__ __forceinline__ int wave_max(int v) {
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_XOR1, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_XOR2, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_HALF_MIRROR, 0xF, 0xF, false));
+  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_MIRROR, 0xF, 0xF, false));
+  v = max(v, (int)xor16_bits((unsigned)v));
+  return max(v, (int)xor32_bits((unsigned)v));
 }
 __device__ __forceinline__ float grp_sum(float v, int G) { return grp_reduce<OpSum>(v, G); }
 __device__ __forceinline__ float grp_max(float v, int G) { return grp_reduce<OpMax>(v, G); }
@@ -719,11 +749,11 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   // sum the shares of the L lanes of this waypoint (butterfly: every copy
   // ends with the same value)
   for (int off = G; off < WAVE; off <<= 1) {
-    phisum += __shfl_xor(phisum, off);
-    if (MODE == EV_RESULT) clr = fminf(clr, __shfl_xor(clr, off));
+    phisum += lane_xor(phisum, off);
+    if (MODE == EV_RESULT) clr = fminf(clr, lane_xor(clr, off));
     if (GRAD) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) o.g[j] += __shfl_xor(o.g[j], off);
+      for (int j = 0; j < NJ; ++j) o.g[j] += lane_xor(o.g[j], off);
     }
   }
   if (tm.W > 1) {
@@ -843,8 +873,7 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
   for (int j = 0; j < NJ; ++j) steep[j] = -g[j] * sc;
 
   // wave-uniform loop bound: the longest history in the wave
-  int cmax = cnt;
-  for (int off = 1; off < WAVE; off <<= 1) cmax = max(cmax, __shfl_xor(cmax, off));
+  const int cmax = wave_max(cnt);
   float q[NJ], a[DS_MAX_HISTORY];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) q[j] = g[j];
