@@ -1,8 +1,9 @@
 // gfx950 kernels of the seeded trajectory optimiser.
 //
-// Mapping: one wavefront owns one tile = 1, 2 or 4 seeds of one problem;
-// lane t of a seed's lane group holds waypoint t (group size G = 64, 32 or
-// 16 >= T).  Per lane the kernel runs the whole per-waypoint chain of the
+// Mapping: one wavefront (or a team of W wavefronts) owns one tile = one
+// seed of one problem; lane t of each lane group holds waypoint t (group
+// size G = 64, 32 or 16 >= T) and the 64 / G groups of a wavefront are
+// copies of the seed that split its spheres.  Per lane the kernel runs the whole per-waypoint chain of the
 // objective (App. A.6): forward kinematics (sincos + 3x4 compositions with
 // the robot table read through the scalar cache), sphere centres, an ESDF
 // gather of one 32-byte corner record per sphere (two 16-byte buffer
