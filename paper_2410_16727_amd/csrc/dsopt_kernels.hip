@@ -104,15 +104,6 @@ __device__ __forceinline__ float grp_reduce(float v, int G) {
   return v;
 }
 
-// Maximum of an int over the whole wavefront (every lane gets it).
-__device__ __forceinline__ int wave_max(int v) {
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_XOR1, 0xF, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_QUAD_XOR2, 0xF, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_HALF_MIRROR, 0xF, 0xF, false));
-  v = max(v, __builtin_amdgcn_update_dpp(0, v, DPP_MIRROR, 0xF, 0xF, false));
-  v = max(v, (int)xor16_bits((unsigned)v));
-  return max(v, (int)xor32_bits((unsigned)v));
-}
 __device__ __forceinline__ float grp_sum(float v, int G) { return grp_reduce<OpSum>(v, G); }
 __device__ __forceinline__ float grp_max(float v, int G) { return grp_reduce<OpMax>(v, G); }
 __device__ __forceinline__ float grp_min(float v, int G) { return grp_reduce<OpMin>(v, G); }
@@ -857,9 +848,16 @@ struct Hist {
 using GHist = Hist<DS_GLOBAL float*>;
 using LHist = Hist<float*>;
 
+// Ring slot of the entry of a given age (0 = newest), 0 <= head < m and
+// 0 <= age < m: one conditional wrap, no integer division.
+__device__ __forceinline__ int ring_slot(int head, int age, int m) {
+  const int s = head - 1 - age;
+  return s < 0 ? s + m : s;
+}
+
 // L-BFGS direction (two-loop recursion over the history ring),
-// steepest-descent restart and infinity-norm cap.  cnt/head are this
-// lane's group's history count and ring head.
+// steepest-descent restart and infinity-norm cap.  cnt/head are the seed's
+// history count and ring head (the same in every lane of the wavefront).
 template <class H>
 __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const float* g, int& cnt,
                                           int head, float* d) {
@@ -873,8 +871,9 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
 #pragma unroll
   for (int j = 0; j < NJ; ++j) steep[j] = -g[j] * sc;
 
-  // wave-uniform loop bound: the longest history in the wave
-  const int cmax = wave_max(cnt);
+  // one seed per wavefront: count and head are wave-uniform
+  const int cmax = __builtin_amdgcn_readfirstlane(cnt);
+  const int hd = __builtin_amdgcn_readfirstlane(head);
   float q[NJ], a[DS_MAX_HISTORY];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) q[j] = g[j];
@@ -882,7 +881,7 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
   // one memory latency overlaps each dependent dot product
   float sn[NJ], yn[NJ], rn = 0.f;
   auto fetch = [&](int k) {
-    const int slot = (head - 1 - k + 2 * m) % m;
+    const int slot = ring_slot(hd, k, m);
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       sn[j] = hist.s(slot, j);
@@ -900,15 +899,13 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
       for (int j = 0; j < NJ; ++j) { s[j] = sn[j]; y[j] = yn[j]; }
       const float rho = rn;
       if (k + 1 < cmax) fetch(k + 1);
-      float dt = grp_sum(dot7(s, q), c.G);
-      bool use = k < cnt;
-      float ak = rho * dt;
-      a[k] = use ? ak : 0.f;
+      const float ak = rho * grp_sum(dot7(s, q), c.G);
+      a[k] = ak;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) q[j] = use ? q[j] - ak * y[j] : q[j];
+      for (int j = 0; j < NJ; ++j) q[j] -= ak * y[j];
     }
   }
-  int newest = (head - 1 + m) % m;
+  const int newest = ring_slot(hd, 0, m);
   float rho_n = hist.rho(newest);
   float yy_n = hist.yy(newest);
   float gamma = 1.f / (rho_n * yy_n);   // s^T y / y^T y
@@ -923,10 +920,9 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
       for (int j = 0; j < NJ; ++j) { s[j] = sn[j]; y[j] = yn[j]; }
       const float rho = rn;
       if (k > 0) fetch(k - 1);
-      float b = rho * grp_sum(dot7(y, q), c.G);
-      bool use = k < cnt;
+      const float b = rho * grp_sum(dot7(y, q), c.G);
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) q[j] = use ? q[j] + s[j] * (a[k] - b) : q[j];
+      for (int j = 0; j < NJ; ++j) q[j] += s[j] * (a[k] - b);
     }
   }
 #pragma unroll
@@ -945,6 +941,213 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
     float f = c.P.dmax / dn;
 #pragma unroll
     for (int j = 0; j < NJ; ++j) d[j] *= f;
+  }
+}
+
+// A team's direction block in LDS: the columns of d, the 2m dot products
+// of the history with g, and the ring-slot matrices s_a.y_b and y_a.y_b
+// (element (a, b) at a * DS_MAX_HISTORY + b).
+constexpr int DL_D = 0, DL_AB = NJ * WAVE, DL_SY = DL_AB + 2 * DS_MAX_HISTORY,
+              DL_YY = DL_SY + DS_MAX_HISTORY * DS_MAX_HISTORY,
+              DL_FLOATS = DL_YY + DS_MAX_HISTORY * DS_MAX_HISTORY;
+
+// The same direction for a team (W > 1), spread over its wavefronts.  The
+// two-loop recursion's result written with inner products (ages k = 0
+// newest .. cnt-1; a_k = s_k.g, b_k = y_k.g; SY(k,j) = s_k.y_j,
+// YY(k,j) = y_k.y_j):
+//   alpha_k = rho_k (a_k - sum_{j<k} alpha_j SY(k,j)),
+//   beta_k  = rho_k (gamma (b_k - sum_i alpha_i YY(k,i))
+//                    + sum_{j>k} (alpha_j - beta_j) SY(j,k)),
+//   H g     = gamma g - sum_k gamma alpha_k y_k + sum_k (alpha_k - beta_k) s_k,
+// gamma = s_0.y_0 / y_0.y_0.  Wavefront w reduces a_k, b_k of the ages
+// k = w mod W; every wavefront then runs the two triangular recurrences
+// (lane i < cnt holds row i) and forms the columns j = w mod W of d.  The
+// slot matrices are maintained at every push (team_push_products).  Every
+// wavefront ends with bitwise the same d and cnt.
+template <class H>
+__device__ __forceinline__ void team_direction(const TileCtx& c, const H& hist, const Team& tm,
+                                               const float* g, int& cnt, int head, float* d,
+                                               DS_LDS float* dl) {
+  const int m = c.P.m;
+  const int cu = __builtin_amdgcn_readfirstlane(cnt);
+  const int hd = __builtin_amdgcn_readfirstlane(head);
+  float gmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) gmax = fmaxf(gmax, fabsf(g[j]));
+  gmax = grp_max(gmax, c.G);
+  const float sc = c.P.delta0 / fmaxf(gmax, 1e-30f);
+  float steep[NJ];
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) steep[j] = -g[j] * sc;
+
+  for (int k = tm.w; k < cu; k += tm.W) {
+    const int b = ring_slot(hd, k, m);
+    float sv[NJ], yv[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      sv[j] = hist.s(b, j);
+      yv[j] = hist.y(b, j);
+    }
+    const float a = grp_sum(dot7(sv, g), c.G);
+    const float bb = grp_sum(dot7(yv, g), c.G);
+    if (c.lane == 0) {
+      dl[DL_AB + k] = a;
+      dl[DL_AB + DS_MAX_HISTORY + k] = bb;
+    }
+  }
+  tm.sync();
+
+  // lane i < DS_MAX_HISTORY holds age i: row i of SY and YY, column i of SY
+  const int li = c.lane < m ? c.lane : 0;
+  const int sli = ring_slot(hd, li, m);
+  float syr[DS_MAX_HISTORY], syc[DS_MAX_HISTORY], yyr[DS_MAX_HISTORY], rh[DS_MAX_HISTORY];
+  float al[DS_MAX_HISTORY], ee[DS_MAX_HISTORY];
+  float acc = 0.f, bq = 0.f;
+  if (cu > 0) {
+    acc = dl[DL_AB + li];
+    bq = dl[DL_AB + DS_MAX_HISTORY + li];
+  }
+#pragma unroll
+  for (int k = 0; k < DS_MAX_HISTORY; ++k) {
+    syr[k] = syc[k] = yyr[k] = rh[k] = 0.f;
+    if (k < cu) {
+      const int sk = ring_slot(hd, k, m);
+      syr[k] = dl[DL_SY + sli * DS_MAX_HISTORY + sk];
+      syc[k] = dl[DL_SY + sk * DS_MAX_HISTORY + sli];
+      yyr[k] = dl[DL_YY + sli * DS_MAX_HISTORY + sk];
+      rh[k] = hist.rho(sk);
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < DS_MAX_HISTORY; ++k) {
+    al[k] = 0.f;
+    if (k < cu) {
+      al[k] = rh[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), k));
+      acc -= al[k] * syr[k];
+    }
+  }
+#pragma unroll
+  for (int k = 0; k < DS_MAX_HISTORY; ++k)
+    if (k < cu) bq -= al[k] * yyr[k];
+  const int s0 = ring_slot(hd, 0, m);
+  const float gamma = cu > 0 ? 1.f / (hist.rho(s0) * hist.yy(s0)) : 0.f;
+  float acc2 = gamma * bq;
+#pragma unroll
+  for (int k = DS_MAX_HISTORY - 1; k >= 0; --k) {
+    ee[k] = 0.f;
+    if (k < cu) {
+      const float be = rh[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc2), k));
+      ee[k] = al[k] - be;
+      acc2 += ee[k] * syc[k];
+    }
+  }
+  if (cu > 0) {
+    unsigned mine = 0;
+    for (int j = tm.w; j < NJ; j += tm.W) mine |= 1u << j;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      if (mine & (1u << j)) {
+        float r = gamma * g[j];
+#pragma unroll
+        for (int k = 0; k < DS_MAX_HISTORY; ++k) {
+          if (k < cu) {
+            const int sk = ring_slot(hd, k, m);
+            r += (-gamma * al[k]) * hist.y(sk, j);
+            r += ee[k] * hist.s(sk, j);
+          }
+        }
+        dl[DL_D + j * WAVE + c.lane] = -r;
+      }
+    }
+  }
+  tm.sync();
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) d[j] = (cu > 0) ? dl[DL_D + j * WAVE + c.lane] : steep[j];
+  const float gtd = grp_sum(dot7(g, d), c.G);
+  if (!(gtd < 0.f)) {
+    cnt = 0;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) d[j] = steep[j];
+  }
+  float dn = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) dn = fmaxf(dn, fabsf(d[j]));
+  dn = grp_max(dn, c.G);
+  if (dn > c.P.dmax) {
+    const float f = c.P.dmax / dn;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) d[j] *= f;
+  }
+}
+
+// Row and column h of the team's slot matrices after (s, y) was pushed into
+// slot h (cnt_new pairs valid): wavefront w takes the slots b = w mod W.
+// Each product is the same grp_sum(dot7(.)) that team_rebuild_products
+// forms, so matrices carried across launches are bitwise the same.
+template <class H>
+__device__ __forceinline__ void team_push_products(const TileCtx& c, const H& hist, const Team& tm,
+                                                   const float* s, const float* y, float sy,
+                                                   float yy, int h, int cnt_new, DS_LDS float* dl) {
+  const int m = c.P.m;
+  const int hu = __builtin_amdgcn_readfirstlane(h);
+  const int cu = __builtin_amdgcn_readfirstlane(cnt_new);
+  for (int b = tm.w; b < m; b += tm.W) {
+    const int age = hu - b < 0 ? hu - b + m : hu - b;
+    if (age >= cu) continue;
+    if (age == 0) {
+      if (c.lane == 0) {
+        dl[DL_SY + hu * DS_MAX_HISTORY + hu] = sy;
+        dl[DL_YY + hu * DS_MAX_HISTORY + hu] = yy;
+      }
+      continue;
+    }
+    float sv[NJ], yv[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      sv[j] = hist.s(b, j);
+      yv[j] = hist.y(b, j);
+    }
+    const float hb = grp_sum(dot7(s, yv), c.G);
+    const float bh = grp_sum(dot7(sv, y), c.G);
+    const float yb = grp_sum(dot7(y, yv), c.G);
+    if (c.lane == 0) {
+      dl[DL_SY + hu * DS_MAX_HISTORY + b] = hb;
+      dl[DL_SY + b * DS_MAX_HISTORY + hu] = bh;
+      dl[DL_YY + hu * DS_MAX_HISTORY + b] = yb;
+      dl[DL_YY + b * DS_MAX_HISTORY + hu] = yb;
+    }
+  }
+}
+
+// The slot matrices of the cnt valid ring entries, formed from the ring
+// (a team resuming a seed in a later launch).
+template <class H>
+__device__ __forceinline__ void team_rebuild_products(const TileCtx& c, const H& hist,
+                                                      const Team& tm, int cnt, int head,
+                                                      DS_LDS float* dl) {
+  const int m = c.P.m;
+  const int cu = __builtin_amdgcn_readfirstlane(cnt);
+  const int hd = __builtin_amdgcn_readfirstlane(head);
+  for (int ka = tm.w; ka < cu; ka += tm.W) {
+    const int a = ring_slot(hd, ka, m);
+    float sa[NJ], ya[NJ];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      sa[j] = hist.s(a, j);
+      ya[j] = hist.y(a, j);
+    }
+    for (int kb = 0; kb < cu; ++kb) {
+      const int b = ring_slot(hd, kb, m);
+      float yb[NJ];
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) yb[j] = hist.y(b, j);
+      const float v = grp_sum(dot7(sa, yb), c.G);
+      const float w = grp_sum(dot7(ya, yb), c.G);
+      if (c.lane == 0) {
+        dl[DL_SY + a * DS_MAX_HISTORY + b] = v;
+        dl[DL_YY + a * DS_MAX_HISTORY + b] = w;
+      }
+    }
   }
 }
 
@@ -1094,6 +1297,9 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
     }
     if (c.P.skip) stage_coarse(pb.sc, lds(coarse_lds), threadIdx.x, tm.W * WAVE);
     tm.sync();
+    // the slot matrices of a resumed ring (read after the direction's first
+    // barrier)
+    if (iter > 0 && n_left > 0) team_rebuild_products(c, hist, tm, cnt, head, lds(dir_lds));
   } else {
     hist.h = c.st + ST_RHO;
     // one wavefront: its LDS accesses complete in order, no barrier needed
@@ -1107,19 +1313,7 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
       trace_row(pb.tr_g, c, iter, g);
       trace_scalar(pb.tr_J, c, iter, J);
       if constexpr (LDS_HIST) {
-        // a team: the first wavefront runs the two-loop recursion, the team
-        // takes its direction (and history count) from LDS
-        DS_LDS float* dl = lds(dir_lds) + c.lane;
-        if (tm.w == 0) {
-          direction(c, hist, g, cnt, head, d);
-#pragma unroll
-          for (int j = 0; j < NJ; ++j) dl[j * WAVE] = d[j];
-          dl[NJ * WAVE] = __int_as_float(cnt);
-        }
-        tm.sync();
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) d[j] = dl[j * WAVE];
-        cnt = __float_as_int(dl[NJ * WAVE]);
+        team_direction(c, hist, tm, g, cnt, head, d, lds(dir_lds));
       } else {
         direction(c, hist, g, cnt, head, d);
       }
@@ -1198,9 +1392,12 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
     float yy = grp_sum(dot7(y, y), c.G);
     if (accept) {
       if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy)) {
+        const int cnt_new = min(cnt + 1, c.P.m);
         if (writer) hist.push(head, s, y, 1.f / sy, yy);
+        if constexpr (LDS_HIST)
+          team_push_products(c, hist, tm, s, y, sy, yy, head, cnt_new, lds(dir_lds));
         head = (head + 1) % c.P.m;
-        cnt = min(cnt + 1, c.P.m);
+        cnt = cnt_new;
       }
 #pragma unroll
       for (int j = 0; j < NJ; ++j) { x[j] = x[j] + alpha * d[j]; g[j] = gt[j]; }
@@ -1647,7 +1844,7 @@ int team_block(int W) { return (W > 1 ? W : WAVES_PER_BLOCK) * WAVE; }
 // buffered), history ring, coarse table and direction broadcast; single
 // wavefronts: one coarse table each
 size_t team_lds(int W) {
-  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS + COARSE_MAX + (NJ + 1) * WAVE) *
+  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS + COARSE_MAX + DL_FLOATS) *
                      sizeof(float)
                : (size_t)WAVES_PER_BLOCK * COARSE_MAX * sizeof(float);
 }
