@@ -961,8 +961,7 @@ constexpr int DL_D = 0, DL_AB = NJ * WAVE, DL_SY = DL_AB + 2 * DS_MAX_HISTORY,
 //   H g     = gamma g - sum_k gamma alpha_k y_k + sum_k (alpha_k - beta_k) s_k,
 // gamma = s_0.y_0 / y_0.y_0.  Wavefront w reduces a_k, b_k of the ages
 // k = w mod W; every wavefront then runs the two triangular recurrences
-// (lane i < cnt holds row i) and forms the columns j = w mod W of d.  The
-// slot matrices are maintained at every push (team_push_products).  Every
+// (lane i < cnt holds row i) and forms the columns j = w mod W of d.  Every
 // wavefront ends with bitwise the same d and cnt.
 template <class H>
 __device__ __forceinline__ void team_direction(const TileCtx& c, const H& hist, const Team& tm,
@@ -980,84 +979,98 @@ __device__ __forceinline__ void team_direction(const TileCtx& c, const H& hist, 
 #pragma unroll
   for (int j = 0; j < NJ; ++j) steep[j] = -g[j] * sc;
 
+  // wavefront w: ages k = w mod W -- a_k, b_k and the newest pair's row and
+  // column of the slot matrices (the same values again when nothing was
+  // pushed since the last direction; older pairs were formed when the
+  // newer of the two was pushed)
+  const int s0 = ring_slot(hd, 0, m);
   for (int k = tm.w; k < cu; k += tm.W) {
     const int b = ring_slot(hd, k, m);
-    float sv[NJ], yv[NJ];
+    float sv[NJ], yv[NJ], s0v[NJ], y0v[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
       sv[j] = hist.s(b, j);
       yv[j] = hist.y(b, j);
+      s0v[j] = hist.s(s0, j);
+      y0v[j] = hist.y(s0, j);
     }
     const float a = grp_sum(dot7(sv, g), c.G);
     const float bb = grp_sum(dot7(yv, g), c.G);
+    const float p0b = grp_sum(dot7(s0v, yv), c.G);   // s_0 . y_k
+    const float pb0 = grp_sum(dot7(sv, y0v), c.G);   // s_k . y_0
+    const float q0b = grp_sum(dot7(y0v, yv), c.G);   // y_0 . y_k
     if (c.lane == 0) {
       dl[DL_AB + k] = a;
       dl[DL_AB + DS_MAX_HISTORY + k] = bb;
+      dl[DL_SY + s0 * DS_MAX_HISTORY + b] = p0b;
+      dl[DL_SY + b * DS_MAX_HISTORY + s0] = pb0;
+      dl[DL_YY + s0 * DS_MAX_HISTORY + b] = q0b;
+      dl[DL_YY + b * DS_MAX_HISTORY + s0] = q0b;
     }
   }
   tm.sync();
 
-  // lane i < DS_MAX_HISTORY holds age i: row i of SY and YY, column i of SY
+  // lane i < cnt holds age i: row i of SY and YY, column i of SY.  Every
+  // operand is loaded unconditionally (valid LDS addresses) and entries of
+  // ages >= cnt are replaced by zeros, so no stale value reaches a sum.
   const int li = c.lane < m ? c.lane : 0;
+  const bool lrow = c.lane < cu;
   const int sli = ring_slot(hd, li, m);
   float syr[DS_MAX_HISTORY], syc[DS_MAX_HISTORY], yyr[DS_MAX_HISTORY], rh[DS_MAX_HISTORY];
   float al[DS_MAX_HISTORY], ee[DS_MAX_HISTORY];
-  float acc = 0.f, bq = 0.f;
-  if (cu > 0) {
-    acc = dl[DL_AB + li];
-    bq = dl[DL_AB + DS_MAX_HISTORY + li];
-  }
+  float acc = lrow ? dl[DL_AB + li] : 0.f;
+  float bq = lrow ? dl[DL_AB + DS_MAX_HISTORY + li] : 0.f;
 #pragma unroll
   for (int k = 0; k < DS_MAX_HISTORY; ++k) {
-    syr[k] = syc[k] = yyr[k] = rh[k] = 0.f;
-    if (k < cu) {
-      const int sk = ring_slot(hd, k, m);
-      syr[k] = dl[DL_SY + sli * DS_MAX_HISTORY + sk];
-      syc[k] = dl[DL_SY + sk * DS_MAX_HISTORY + sli];
-      yyr[k] = dl[DL_YY + sli * DS_MAX_HISTORY + sk];
-      rh[k] = hist.rho(sk);
-    }
+    const bool v = k < cu;
+    const int sk = ring_slot(hd, k < m ? k : 0, m);
+    const float a = dl[DL_SY + sli * DS_MAX_HISTORY + sk];
+    const float b = dl[DL_SY + sk * DS_MAX_HISTORY + sli];
+    const float e = dl[DL_YY + sli * DS_MAX_HISTORY + sk];
+    const float r = hist.rho(sk);
+    syr[k] = (v && lrow) ? a : 0.f;
+    syc[k] = (v && lrow) ? b : 0.f;
+    yyr[k] = (v && lrow) ? e : 0.f;
+    rh[k] = v ? r : 0.f;
   }
+  // alpha: forward substitution, one age per step (lane k is final at step k)
 #pragma unroll
   for (int k = 0; k < DS_MAX_HISTORY; ++k) {
-    al[k] = 0.f;
-    if (k < cu) {
-      al[k] = rh[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), k));
-      acc -= al[k] * syr[k];
-    }
+    al[k] = rh[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc), k));
+    acc -= al[k] * syr[k];
   }
 #pragma unroll
-  for (int k = 0; k < DS_MAX_HISTORY; ++k)
-    if (k < cu) bq -= al[k] * yyr[k];
-  const int s0 = ring_slot(hd, 0, m);
+  for (int k = 0; k < DS_MAX_HISTORY; ++k) bq -= al[k] * yyr[k];
   const float gamma = cu > 0 ? 1.f / (hist.rho(s0) * hist.yy(s0)) : 0.f;
+  // beta: backward substitution from the oldest age
   float acc2 = gamma * bq;
 #pragma unroll
   for (int k = DS_MAX_HISTORY - 1; k >= 0; --k) {
-    ee[k] = 0.f;
-    if (k < cu) {
-      const float be = rh[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc2), k));
-      ee[k] = al[k] - be;
-      acc2 += ee[k] * syc[k];
-    }
+    const float be = rh[k] * __int_as_float(__builtin_amdgcn_readlane(__float_as_int(acc2), k));
+    ee[k] = al[k] - be;
+    acc2 += ee[k] * syc[k];
   }
-  if (cu > 0) {
-    unsigned mine = 0;
-    for (int j = tm.w; j < NJ; j += tm.W) mine |= 1u << j;
+  // the columns j = w mod W of d: all operands loaded before the sums
+  for (int j0 = tm.w; j0 < NJ; j0 += tm.W) {
 #pragma unroll
     for (int j = 0; j < NJ; ++j) {
-      if (mine & (1u << j)) {
-        float r = gamma * g[j];
+      if (j != j0) continue;
+      float sv[DS_MAX_HISTORY], yv[DS_MAX_HISTORY];
 #pragma unroll
-        for (int k = 0; k < DS_MAX_HISTORY; ++k) {
-          if (k < cu) {
-            const int sk = ring_slot(hd, k, m);
-            r += (-gamma * al[k]) * hist.y(sk, j);
-            r += ee[k] * hist.s(sk, j);
-          }
-        }
-        dl[DL_D + j * WAVE + c.lane] = -r;
+      for (int k = 0; k < DS_MAX_HISTORY; ++k) {
+        const int sk = ring_slot(hd, k < m ? k : 0, m);
+        const bool v = k < cu;
+        const float a = hist.s(sk, j), b = hist.y(sk, j);
+        sv[k] = v ? a : 0.f;
+        yv[k] = v ? b : 0.f;
       }
+      float r = gamma * g[j];
+#pragma unroll
+      for (int k = 0; k < DS_MAX_HISTORY; ++k) {
+        r += (-gamma * al[k]) * yv[k];
+        r += ee[k] * sv[k];
+      }
+      dl[DL_D + j * WAVE + c.lane] = -r;
     }
   }
   tm.sync();
@@ -1080,47 +1093,9 @@ __device__ __forceinline__ void team_direction(const TileCtx& c, const H& hist, 
   }
 }
 
-// Row and column h of the team's slot matrices after (s, y) was pushed into
-// slot h (cnt_new pairs valid): wavefront w takes the slots b = w mod W.
-// Each product is the same grp_sum(dot7(.)) that team_rebuild_products
-// forms, so matrices carried across launches are bitwise the same.
-template <class H>
-__device__ __forceinline__ void team_push_products(const TileCtx& c, const H& hist, const Team& tm,
-                                                   const float* s, const float* y, float sy,
-                                                   float yy, int h, int cnt_new, DS_LDS float* dl) {
-  const int m = c.P.m;
-  const int hu = __builtin_amdgcn_readfirstlane(h);
-  const int cu = __builtin_amdgcn_readfirstlane(cnt_new);
-  for (int b = tm.w; b < m; b += tm.W) {
-    const int age = hu - b < 0 ? hu - b + m : hu - b;
-    if (age >= cu) continue;
-    if (age == 0) {
-      if (c.lane == 0) {
-        dl[DL_SY + hu * DS_MAX_HISTORY + hu] = sy;
-        dl[DL_YY + hu * DS_MAX_HISTORY + hu] = yy;
-      }
-      continue;
-    }
-    float sv[NJ], yv[NJ];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      sv[j] = hist.s(b, j);
-      yv[j] = hist.y(b, j);
-    }
-    const float hb = grp_sum(dot7(s, yv), c.G);
-    const float bh = grp_sum(dot7(sv, y), c.G);
-    const float yb = grp_sum(dot7(y, yv), c.G);
-    if (c.lane == 0) {
-      dl[DL_SY + hu * DS_MAX_HISTORY + b] = hb;
-      dl[DL_SY + b * DS_MAX_HISTORY + hu] = bh;
-      dl[DL_YY + hu * DS_MAX_HISTORY + b] = yb;
-      dl[DL_YY + b * DS_MAX_HISTORY + hu] = yb;
-    }
-  }
-}
-
 // The slot matrices of the cnt valid ring entries, formed from the ring
-// (a team resuming a seed in a later launch).
+// (a team resuming a seed in a later launch): the same grp_sum(dot7(.))
+// products the direction forms, so a resumed run is bitwise the same.
 template <class H>
 __device__ __forceinline__ void team_rebuild_products(const TileCtx& c, const H& hist,
                                                       const Team& tm, int cnt, int head,
@@ -1392,12 +1367,9 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
     float yy = grp_sum(dot7(y, y), c.G);
     if (accept) {
       if (sy > 1e-10f * sqrtf(ss) * sqrtf(yy)) {
-        const int cnt_new = min(cnt + 1, c.P.m);
         if (writer) hist.push(head, s, y, 1.f / sy, yy);
-        if constexpr (LDS_HIST)
-          team_push_products(c, hist, tm, s, y, sy, yy, head, cnt_new, lds(dir_lds));
         head = (head + 1) % c.P.m;
-        cnt = cnt_new;
+        cnt = min(cnt + 1, c.P.m);
       }
 #pragma unroll
       for (int j = 0; j < NJ; ++j) { x[j] = x[j] + alpha * d[j]; g[j] = gt[j]; }
@@ -1465,7 +1437,8 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   if (max_iters_dev) max_iters = *max_iters_dev;   // serving: set per replay
   Team tm;
   tm.W = TEAM ? pp->waves : 1;
-  tm.w = TEAM ? (int)(threadIdx.x / WAVE) : 0;
+  // wave-uniform (scalar) index, so loops over a wavefront's share stay scalar
+  tm.w = TEAM ? __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE)) : 0;
   tm.lds = s_dyn;
   tm.buf = 0;
   for (;;) {
@@ -1573,7 +1546,7 @@ __device__ __forceinline__ int seed_of(int W, float* team_lds, Team& tm) {
   tm.buf = 0;
   if (W > 1) {
     tm.W = W;
-    tm.w = threadIdx.x / WAVE;
+    tm.w = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
     tm.lds = team_lds;
     return blockIdx.x;
   }
