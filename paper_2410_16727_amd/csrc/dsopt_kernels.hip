@@ -658,16 +658,21 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     coll += P.ws * selfsum;
   }
   // goal pose, joint limits and smoothness: the same for every copy of the
-  // waypoint, so one wavefront of the team computes them and only its first
-  // copy adds them to its share before the sums below -- the second
-  // wavefront (off the first one's path, which also runs the direction),
-  // except in the result pass, whose goal errors the first one writes
-  const int xw = (MODE == EV_RESULT || tm.W == 1) ? 0 : 1;
-  if (tm.w == xw) {
+  // waypoint, so one wavefront of the team computes each and only its first
+  // copy adds them to its share before the sums below -- the goal on the
+  // second wavefront, limits and smoothness on the third (off the first
+  // one's path), except in the result pass, whose goal errors the first
+  // one writes
+  const int xg = (MODE == EV_RESULT || tm.W == 1) ? 0 : 1;
+  const int xl = (MODE == EV_RESULT || tm.W < 3) ? xg : 2;
+  if (tm.w == xg || tm.w == xl) {
     const bool first = lane < G;
+    const bool last = (t == T - 1);
     float ge[NJ];
 #pragma unroll
     for (int j = 0; j < NJ; ++j) ge[j] = 0.f;
+    float extra_g = 0.f, extra_l = 0.f;
+    if (tm.w == xg) {
     // end effector and goal pose
     const float* E = rb->Fee;
     float Re[9], pe[3];
@@ -682,8 +687,8 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     float tr = 0.f;
 #pragma unroll
     for (int k = 0; k < 9; ++k) tr += goal.Rd[k] * Re[k];
-    const bool last = (t == T - 1);
-    float goal_cost = P.wp * (ex * ex + ey * ey + ez * ez) + P.wr * (3.f - tr) * 0.25f;
+    const float goal_cost = P.wp * (ex * ex + ey * ey + ez * ez) + P.wr * (3.f - tr) * 0.25f;
+    extra_g = last ? goal_cost : 0.f;
     if (GRAD && last) {
       // force 2 w_p e at p_ee and torque -(w_r/4) w, w = vee(M - M^T), M = R_ee R_d^T
       float M[9];
@@ -720,6 +725,8 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       float wx = M5 - M7, wy = M6 - M2, wz = M1 - M3;
       o.rerr = atan2f(0.5f * sqrtf(wx * wx + wy * wy + wz * wz), 0.5f * (tr - 1.f));
     }
+    }
+    if (tm.w == xl) {
     // joint limits
     float lim = 0.f;
 #pragma unroll
@@ -730,8 +737,9 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       if (GRAD) ge[j] += 2.f * P.wl * (hp - lp);
     }
     float sm = smoothness<GRAD>(P, q, t, T, ge);
-    const float extra = P.wl * lim + sm + (last ? goal_cost : 0.f);
-    coll += first ? extra : 0.f;
+    extra_l = P.wl * lim + sm;
+    }
+    coll += first ? extra_l + extra_g : 0.f;
     if (GRAD) {
 #pragma unroll
       for (int j = 0; j < NJ; ++j) o.g[j] += first ? ge[j] : 0.f;
@@ -748,29 +756,39 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       for (int j = 0; j < NJ; ++j) o.g[j] += lane_xor(o.g[j], off);
     }
   }
-  if (tm.W > 1) {
-    // ... and of the W wavefronts, summed in wavefront order
+  if (GRAD && tm.W > 1) {
+    // ... and of the W wavefronts, summed in wavefront order: wavefront w
+    // sums the components c = w mod W of the team (into wavefront 0's row),
+    // then every wavefront takes the sums
+    constexpr int NC = NJ + 1;
+    float* base = tm.lds + (tm.buf * tm.W * PART) * WAVE + lane;
+    float* mine = base + tm.w * PART * WAVE;
+    mine[0] = phisum;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) mine[(1 + j) * WAVE] = o.g[j];
+    tm.sync();
+    for (int cc = tm.w; cc < NC; cc += tm.W) {
+      float v = base[cc * WAVE];
+      for (int u = 1; u < tm.W; ++u) v += base[(u * PART + cc) * WAVE];
+      base[cc * WAVE] = v;
+    }
+    tm.sync();
+    phisum = base[0];
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) o.g[j] = base[(1 + j) * WAVE];
+    tm.buf ^= 1;
+  } else if (tm.W > 1) {
+    // (cost and result passes: every wavefront sums all shares)
     float* mine = tm.lds + ((tm.buf * tm.W + tm.w) * PART) * WAVE + lane;
     mine[0] = phisum;
-    if (GRAD) {
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) mine[(1 + j) * WAVE] = o.g[j];
-    }
     if (MODE == EV_RESULT) mine[(1 + NJ) * WAVE] = clr;
     tm.sync();
     const float* all = tm.lds + (tm.buf * tm.W * PART) * WAVE + lane;
     phisum = all[0];
-#pragma unroll
-    for (int j = 0; j < NJ; ++j)
-      if (GRAD) o.g[j] = all[(1 + j) * WAVE];
     if (MODE == EV_RESULT) clr = all[(1 + NJ) * WAVE];
     for (int v = 1; v < tm.W; ++v) {
       const float* pv = all + v * PART * WAVE;
       phisum += pv[0];
-      if (GRAD) {
-#pragma unroll
-        for (int j = 0; j < NJ; ++j) o.g[j] += pv[(1 + j) * WAVE];
-      }
       if (MODE == EV_RESULT) clr = fminf(clr, pv[(1 + NJ) * WAVE]);
     }
     tm.buf ^= 1;
