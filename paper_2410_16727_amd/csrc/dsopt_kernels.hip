@@ -581,7 +581,9 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
         sphere_term<MODE>(P, S, cl, pa_[l], pz_[l], pr_[l], pc_[l][0], pc_[l][1], pc_[l][2],
                           phisum, clr, FM);
       }
-      if (GRAD) project(tw, l, FM, g);
+      // a link none of whose samples reached the hinge in this wavefront
+      // has a zero wrench everywhere: its projection would add zeros
+      if (GRAD && __any(pv_[l])) project(tw, l, FM, g);
     }
   }
 }
