@@ -489,7 +489,7 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
   p[0] = p[1] = p[2] = 0.f;
   // PIPE: the lane's sample of every link
   float4 pa_[PIPE ? NJ : 1], pz_[PIPE ? NJ : 1];
-  float pc_[PIPE ? NJ : 1][3], pr_[PIPE ? NJ : 1];
+  float pc_[PIPE ? NJ : 1][3], pr_[PIPE ? NJ : 1], pcm_[PIPE ? NJ : 1];
   bool pv_[PIPE ? NJ : 1];
 #pragma unroll
   for (int l = 0; l < NJ; ++l) {
@@ -523,14 +523,9 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
         pc_[l][1] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
         pc_[l][2] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
         pr_[l] = sp.w;
-        Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
-        if (SKIP && far_sample(S, cl, sp.w, P.far)) {
-          pv_[l] = false;   // zero hinge, zero gradient: nothing to add
-        } else {
-          pa_[l] = load_rec(S, cl.off);
-          pz_[l] = load_rec(S, cl.off + 16);
-          ++ng;
-        }
+        // the coarse minimum is read here and tested after the chain, so
+        // no link waits for its lookup before the next frame
+        if (SKIP) pcm_[l] = S.cm[locate(S, pc_[l][0], pc_[l][1], pc_[l][2]).cidx];
       }
       continue;
     }
@@ -573,6 +568,20 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
     if (GRAD) project(tw, l, FM, g);
   }
   if (PIPE) {
+    // issue the record loads of the samples that can reach the hinge
+#pragma unroll
+    for (int l = 0; l < NJ; ++l) {
+      if (pv_[l]) {
+        if (SKIP && pcm_[l] >= pr_[l] + P.far) {
+          pv_[l] = false;   // zero hinge, zero gradient: nothing to add
+        } else {
+          const Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
+          pa_[l] = load_rec(S, cl.off);
+          pz_[l] = load_rec(S, cl.off + 16);
+          ++ng;
+        }
+      }
+    }
 #pragma unroll
     for (int l = 0; l < NJ; ++l) {
       float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
