@@ -877,6 +877,38 @@ struct Hist {
 using GHist = Hist<DS_GLOBAL float*>;
 using LHist = Hist<float*>;
 
+// Steepest-descent step scaled so that its largest entry is delta0 (the
+// restart direction).
+__device__ __forceinline__ void steepest(const TileCtx& c, const float* g, float* d) {
+  float gmax = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) gmax = fmaxf(gmax, fabsf(g[j]));
+  gmax = grp_max(gmax, c.G);
+  const float sc = c.P.delta0 / fmaxf(gmax, 1e-30f);
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) d[j] = -g[j] * sc;
+}
+
+// A direction's descent test, restart and infinity-norm cap (the seed's
+// values are the same in every lane, so the tests are taken wave-uniformly).
+__device__ __forceinline__ void restart_and_cap(const TileCtx& c, const float* g, int& cnt,
+                                                float* d) {
+  const float gtd = grp_sum(dot7(g, d), c.G);
+  if (!__builtin_amdgcn_readfirstlane(gtd < 0.f ? 1 : 0)) {
+    cnt = 0;
+    steepest(c, g, d);
+  }
+  float dn = 0.f;
+#pragma unroll
+  for (int j = 0; j < NJ; ++j) dn = fmaxf(dn, fabsf(d[j]));
+  dn = grp_max(dn, c.G);
+  if (dn > c.P.dmax) {
+    const float f = c.P.dmax / dn;
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) d[j] *= f;
+  }
+}
+
 // Ring slot of the entry of a given age (0 = newest), 0 <= head < m and
 // 0 <= age < m: one conditional wrap, no integer division.
 __device__ __forceinline__ int ring_slot(int head, int age, int m) {
@@ -891,15 +923,6 @@ template <class H>
 __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const float* g, int& cnt,
                                           int head, float* d) {
   const int m = c.P.m;
-  float gmax = 0.f;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) gmax = fmaxf(gmax, fabsf(g[j]));
-  gmax = grp_max(gmax, c.G);
-  float sc = c.P.delta0 / fmaxf(gmax, 1e-30f);
-  float steep[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) steep[j] = -g[j] * sc;
-
   // one seed per wavefront: count and head are wave-uniform
   const int cmax = __builtin_amdgcn_readfirstlane(cnt);
   const int hd = __builtin_amdgcn_readfirstlane(head);
@@ -954,23 +977,13 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
       for (int j = 0; j < NJ; ++j) q[j] += s[j] * (a[k] - b);
     }
   }
+  if (cmax > 0) {
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) d[j] = (cnt > 0) ? -q[j] : steep[j];
-  float gtd = grp_sum(dot7(g, d), c.G);
-  if (!(gtd < 0.f)) {
-    cnt = 0;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) d[j] = steep[j];
+    for (int j = 0; j < NJ; ++j) d[j] = -q[j];
+  } else {
+    steepest(c, g, d);
   }
-  float dn = 0.f;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) dn = fmaxf(dn, fabsf(d[j]));
-  dn = grp_max(dn, c.G);
-  if (dn > c.P.dmax) {
-    float f = c.P.dmax / dn;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) d[j] *= f;
-  }
+  restart_and_cap(c, g, cnt, d);
 }
 
 // A team's direction block in LDS: the columns of d, the 2m dot products
@@ -999,14 +1012,6 @@ __device__ __forceinline__ void team_direction(const TileCtx& c, const H& hist, 
   const int m = c.P.m;
   const int cu = __builtin_amdgcn_readfirstlane(cnt);
   const int hd = __builtin_amdgcn_readfirstlane(head);
-  float gmax = 0.f;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) gmax = fmaxf(gmax, fabsf(g[j]));
-  gmax = grp_max(gmax, c.G);
-  const float sc = c.P.delta0 / fmaxf(gmax, 1e-30f);
-  float steep[NJ];
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) steep[j] = -g[j] * sc;
 
   // wavefront w: ages k = w mod W -- a_k, b_k and the newest pair's row and
   // column of the slot matrices (the same values again when nothing was
@@ -1103,23 +1108,13 @@ __device__ __forceinline__ void team_direction(const TileCtx& c, const H& hist, 
     }
   }
   tm.sync();
+  if (cu > 0) {
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) d[j] = (cu > 0) ? dl[DL_D + j * WAVE + c.lane] : steep[j];
-  const float gtd = grp_sum(dot7(g, d), c.G);
-  if (!(gtd < 0.f)) {
-    cnt = 0;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) d[j] = steep[j];
+    for (int j = 0; j < NJ; ++j) d[j] = dl[DL_D + j * WAVE + c.lane];
+  } else {
+    steepest(c, g, d);
   }
-  float dn = 0.f;
-#pragma unroll
-  for (int j = 0; j < NJ; ++j) dn = fmaxf(dn, fabsf(d[j]));
-  dn = grp_max(dn, c.G);
-  if (dn > c.P.dmax) {
-    const float f = c.P.dmax / dn;
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) d[j] *= f;
-  }
+  restart_and_cap(c, g, cnt, d);
 }
 
 // The slot matrices of the cnt valid ring entries, formed from the ring
@@ -1256,6 +1251,9 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
   const int n_iters = c.pb->n_iters;
   DS_GLOBAL int* sti = (DS_GLOBAL int*)c.st;
   const ProbDev& pb = *c.pb;
+  // the trace buffers are all set or all null: one flag per tile, so the
+  // iteration does not reload the pointers
+  const bool tracing = pb.tr_x != nullptr;
 
   float x[NJ], g[NJ], d[NJ], xe[NJ], gt[NJ];
   float J = 0.f, Jt = 0.f, gtd = 0.f, alpha = 0.f;
@@ -1313,15 +1311,17 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
   for (;;) {
     if (phase == PH_DIR) {
       if (n_left <= 0) break;
-      trace_row(pb.tr_x, c, iter, x);
-      trace_row(pb.tr_g, c, iter, g);
-      trace_scalar(pb.tr_J, c, iter, J);
+      if (tracing) {
+        trace_row(pb.tr_x, c, iter, x);
+        trace_row(pb.tr_g, c, iter, g);
+        trace_scalar(pb.tr_J, c, iter, J);
+      }
       if constexpr (LDS_HIST) {
         team_direction(c, hist, tm, g, cnt, head, d, lds(dir_lds));
       } else {
         direction(c, hist, g, cnt, head, d);
       }
-      trace_row(pb.tr_d, c, iter, d);
+      if (tracing) trace_row(pb.tr_d, c, iter, d);
       gtd = grp_sum(dot7(g, d), c.G);
 #pragma unroll
       for (int j = 0; j < NJ; ++j) xe[j] = x[j] + d[j];
@@ -1382,7 +1382,7 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
     }
     if (!update_now) continue;
     // history update and step
-    trace_scalar(pb.tr_a, c, iter, alpha);
+    if (tracing) trace_scalar(pb.tr_a, c, iter, alpha);
     const bool accept = chosen >= 0;
     float s[NJ], y[NJ];
 #pragma unroll
