@@ -158,6 +158,31 @@ def test_lockstep_iterations(key, waves):
     su.plan.release(7)
 
 
+class ShortHistory(Setup):
+    def __init__(self, key, iters, waves, m):
+        self.key = key
+        self.ps = dict(P, history=m)
+        self.robot = configs.robot(key)
+        self.scene = configs.scenes(key, only={0})[0]
+        self.prob = configs.problems(key)[0]
+        self.iters = iters
+        self.plan = dsopt.Plan(self.robot, dict(self.ps, waves_per_seed=waves), iters, 512 << 20)
+        self.plan.upload_scene(0, self.scene.grid, self.scene.voxel, self.scene.origin)
+        self.O = oracle.Oracle(self.robot, self.scene, params.as_list(self.ps), threads=8)
+
+
+@pytest.mark.parametrize("waves,m", [(8, 3), (2, 5), (1, 3), (8, 1), (4, 7)])
+def test_lockstep_short_history(waves, m):
+    """History memories below 8 (the ring wraps at m; a team's inner-product
+    direction and a single wavefront's two-loop) against the oracle's FP64
+    two-loop on the same history, iteration by iteration."""
+    su = ShortHistory("B", 40, waves, m)
+    say(f"short history m={m} W={waves}")
+    seeds, tr = run_traced(su, S=8, tag=9)
+    lockstep_check(su, tr, seeds.shape[0])
+    su.plan.close()
+
+
 @pytest.mark.parametrize("key,waves", [("A", 1), ("B", 1), ("B", 8)])
 def test_flags_match_oracle_on_final_trajectories(key, waves):
     su = setup(key, waves=waves)

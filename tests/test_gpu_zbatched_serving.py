@@ -126,13 +126,17 @@ def test_full_batched_workload_flags_vs_oracle(batchD):
     say(f"checked {n_checked} sampled seeds")
 
 
-@pytest.mark.parametrize("waves", [1, 8])
-def test_serving_matches_alone_bitwise(waves):
+@pytest.mark.parametrize("waves,m", [(1, 8), (8, 8), (8, 3), (2, 5)])
+def test_serving_matches_alone_bitwise(waves, m):
+    """Served in 7-iteration blocks (every request resumes in later
+    launches; a team rebuilds its history products from the ring, also with
+    a short, often wrapped ring) vs alone in one launch: the same bits."""
     key = "B"
     robot = configs.robot(key)
     scene = configs.scenes(key, only={0})[0]
     prob = configs.problems(key)[0]
-    plan = dsopt.Plan(robot, dict(P, waves_per_seed=waves), 30, 1 << 30, block_iters=7)
+    plan = dsopt.Plan(robot, dict(P, waves_per_seed=waves, history=m), 30, 1 << 30,
+                      block_iters=7)
     plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
     rng = np.random.default_rng(5)
     reqs = []
