@@ -757,8 +757,11 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     }
   }
   phisum = coll;
+  // a team's gradient pass sums the copies inside its reduce-scatter below
+  const bool scatter = GRAD && tm.W > 1;
   // sum the shares of the L lanes of this waypoint (butterfly: every copy
   // ends with the same value)
+  if (!scatter)
   for (int off = G; off < WAVE; off <<= 1) {
     phisum += lane_xor(phisum, off);
     if (MODE == EV_RESULT) clr = fminf(clr, lane_xor(clr, off));
@@ -767,10 +770,11 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       for (int j = 0; j < NJ; ++j) o.g[j] += lane_xor(o.g[j], off);
     }
   }
-  if (GRAD && tm.W > 1) {
+  if (scatter) {
     // ... and of the W wavefronts, summed in wavefront order: wavefront w
-    // sums the components c = w mod W of the team (into wavefront 0's row),
-    // then every wavefront takes the sums
+    // sums the components c = w mod W of the team (into wavefront 0's row)
+    // -- each copy's lanes separately, then the copies by the butterfly --
+    // and every wavefront takes the sums
     constexpr int NC = NJ + 1;
     float* base = tm.lds + (tm.buf * tm.W * PART) * WAVE + lane;
     float* mine = base + tm.w * PART * WAVE;
@@ -781,6 +785,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     for (int cc = tm.w; cc < NC; cc += tm.W) {
       float v = base[cc * WAVE];
       for (int u = 1; u < tm.W; ++u) v += base[(u * PART + cc) * WAVE];
+      for (int off = G; off < WAVE; off <<= 1) v += lane_xor(v, off);
       base[cc * WAVE] = v;
     }
     tm.sync();
