@@ -1,7 +1,7 @@
 """GPU parity: the gfx950 library against the FP64 oracle on the same
 seeded inputs, through the C ABI.
 
-Tolerances (spec contract of this path): sphere centres within
+Tolerances (the FP32 path against the FP64 oracle): sphere centres within
 1e-5 m; costs within 1e-4 relative; gradients within 1e-4 of the gradient
 scale (the larger of |g|_inf and the largest per-element sum of absolute
 contributions -- the float32 sum cannot do better than that scale) plus the
