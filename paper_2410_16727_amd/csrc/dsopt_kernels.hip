@@ -1593,7 +1593,7 @@ __device__ __forceinline__ int seed_of(int W, float* team_lds, Team& tm) {
 // Objective (and gradient) of arbitrary trajectories: one wavefront (or a
 // team) per seed group of G lanes (G = smallest of 16/32/64 holding T).
 template <bool EXT>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(MAX_TEAM * WAVE)
 k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const ProbDev* __restrict__ pb, const float* __restrict__ X, int S, int T, int G,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
@@ -1635,7 +1635,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
 // Guidance: n gradient steps x <- x - alpha * g on every trajectory, one
 // wavefront (or a team) per seed (same evaluation as the optimiser).
 template <bool EXT>
-__global__ void __launch_bounds__(BLOCK)
+__global__ void __launch_bounds__(MAX_TEAM * WAVE)
 k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
         int n_steps, float* __restrict__ J_out, int W) {
@@ -1908,8 +1908,10 @@ hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipSt
 // give at least WAVES_PER_BLOCK wavefronts per CU, else teams of up to
 // WAVES_PER_BLOCK wavefronts per seed.
 static int cost_team(int S, int cu_count) {
+  // up to 8 wavefronts per seed while the seeds alone would leave the CUs
+  // below two wavefronts per SIMD
   int W = 1;
-  while (W < WAVES_PER_BLOCK && (long long)S * W < (long long)WAVES_PER_BLOCK * cu_count) W *= 2;
+  while (W < MAX_TEAM && (long long)S * W < (long long)2 * WAVES_PER_BLOCK * cu_count) W *= 2;
   return W;
 }
 
