@@ -343,9 +343,10 @@ def run_serving(args, dsopt, torch, configs, params):
 
 def run_differentiation(args, dsopt, torch, configs, params):
     """Cost + gradient of 256 seeds x 64 waypoints (60 spheres, 200^3) in
-    one call, and the same through the autograd function (forward cost,
-    backward adjoint with kinematics recomputed), timed with events on the
-    stream both run on."""
+    one call, and the same through the autograd function (forward: cost and
+    adjoint gradient in one launch, kinematics recomputed; backward: the
+    saved gradient scaled by dJ), timed with events on the stream both run
+    on."""
     from paper_2410_16727_amd.autograd import trajectory_cost
     key = "C"
     robot = configs.robot(key)

@@ -339,7 +339,7 @@ class Plan:
         import torch
         S, T, _ = X.shape
         J = torch.empty(S, dtype=torch.float32, device=X.device)
-        dX = torch.zeros_like(X)
+        dX = torch.empty_like(X)   # every element is written (row 0 as zero)
         pr = problem_struct(scene, q_start, goal)
         check(self.lib.ds_cost_grad(self.h, C.byref(pr), _ptr(X), S, T, _ptr(dJ), _ptr(J),
                                     _ptr(dX), _stream(stream)))

@@ -233,6 +233,15 @@ def test_autograd_matches_oracle_gradient():
     O = oracle.Oracle(robot, scene, params.as_list(), threads=8)
     ref = O.cost(prob.q_start, prob.goal, X.astype(np.float64), grad=True, absg=True)
     assert np.abs(J.detach().cpu().numpy() - ref["J"]).max() / ref["J"].min() < 1e-4
+    # backward scales the gradient saved by forward: the same bits as the
+    # kernel given the weights
+    _, Gw = plan.cost_grad(0, prob.q_start, prob.goal, Xt.detach(), w)
+    assert torch.equal(Xt.grad, Gw)
+    # without a gradient the forward runs the cost-only kernel (its team sum
+    # is ordered differently: equal up to rounding)
+    with torch.no_grad():
+        Jc = trajectory_cost(Xt.detach(), plan, 0, prob.q_start, prob.goal)
+    assert torch.allclose(Jc, J.detach(), rtol=1e-6, atol=0)
     G = Xt.grad.cpu().numpy()
     wn = w.cpu().numpy()
     for s in range(16):
