@@ -274,11 +274,20 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   size_t off_t = ((size_t)n * sizeof(ProbDev) + 255) / 256 * 256;
   TileDev* td_dev = reinterpret_cast<TileDev*>(tab + off_t);
   int* counter = reinterpret_cast<int*>(tab + off_t + ((size_t)total_tiles * sizeof(TileDev) + 255) / 256 * 256);
-  if (int rc = upload(p, pd_dev, pd.data(), n * sizeof(ProbDev), s)) return rc;
-  if (int rc = upload(p, td_dev, td.data(), td.size() * sizeof(TileDev), s)) return rc;
-  HIP_TRY(launch_zero_i32(counter, 1, s));
-  // fresh tiles: iteration counters and seed results start at zero
-  HIP_TRY(launch_tile_reset(td_dev, pd_dev, total_tiles, s));
+  // problem and tile tables in one copy (they are adjacent in the arena)
+  {
+    std::vector<uint8_t> tabh(off_t + td.size() * sizeof(TileDev), 0);
+    std::memcpy(tabh.data(), pd.data(), n * sizeof(ProbDev));
+    std::memcpy(tabh.data() + off_t, td.data(), td.size() * sizeof(TileDev));
+    if (int rc = upload(p, tab, tabh.data(), tabh.size(), s)) return rc;
+  }
+  // fresh tiles (iteration counters and seed results start at zero) and an
+  // empty tile queue
+  if (total_tiles > 0) {
+    HIP_TRY(launch_tile_reset(td_dev, pd_dev, total_tiles, counter, s));
+  } else {
+    HIP_TRY(launch_zero_i32(counter, 1, s));
+  }
   const int W = p->params.waves;
   const int per_block = W > 1 ? 1 : WAVES_PER_BLOCK;
   int blocks = (total_tiles + per_block - 1) / per_block;

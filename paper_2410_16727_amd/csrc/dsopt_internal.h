@@ -131,7 +131,9 @@ hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* 
 hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
                           hipStream_t s);
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
-hipError_t launch_tile_reset(const TileDev* tiles, const ProbDev* probs, int n_tiles,
+// Fresh tiles (iteration counters, seed results) and the tile queue counter
+// (n_tiles >= 1).
+hipError_t launch_tile_reset(const TileDev* tiles, const ProbDev* probs, int n_tiles, int* counter,
                              hipStream_t s);
 hipError_t launch_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz, float voxel,
                                       float* w0, float* w1, float* w2, float* w3, float* out,

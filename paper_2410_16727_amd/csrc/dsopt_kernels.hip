@@ -1565,7 +1565,9 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
 // the seed) and its seed's result record (counters accumulate over
 // launches).  One workgroup of one wavefront per tile.
 __global__ void __launch_bounds__(64) k_tile_reset(const TileDev* __restrict__ tiles,
-                                                   const ProbDev* __restrict__ probs) {
+                                                   const ProbDev* __restrict__ probs,
+                                                   int* __restrict__ counter) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;   // the tile queue
   const TileDev td = tiles[blockIdx.x];
   reinterpret_cast<int*>(td.state)[ST_ITER + threadIdx.x] = 0;
   constexpr int W = (int)(sizeof(ds_seed_result) / sizeof(int));
@@ -1893,9 +1895,9 @@ int optimize_blocks_per_cu(int W, bool ext) {
   return n > 0 ? n : 1;
 }
 
-hipError_t launch_tile_reset(const TileDev* tiles, const ProbDev* probs, int n_tiles,
+hipError_t launch_tile_reset(const TileDev* tiles, const ProbDev* probs, int n_tiles, int* counter,
                              hipStream_t s) {
-  hipLaunchKernelGGL(k_tile_reset, dim3(n_tiles), dim3(64), 0, s, tiles, probs);
+  hipLaunchKernelGGL(k_tile_reset, dim3(n_tiles), dim3(64), 0, s, tiles, probs, counter);
   return hipGetLastError();
 }
 
