@@ -62,6 +62,12 @@ def lib():
                                    D, D, D, D, C.c_int]
         L.orc_minimize.argtypes = [OBJ_CB, C.c_void_p, D, D, C.c_int, C.c_int, D, D]
         L.orc_two_loop.argtypes = [D, D, D, C.c_int, C.c_int, D]
+        L.orc_choose_step.restype = C.c_int
+        L.orc_choose_step.argtypes = [D, C.c_double, C.c_double, D, C.c_int, D]
+        L.orc_direction.restype = C.c_int
+        L.orc_direction.argtypes = [D, D, D, D, C.c_int, C.c_int, D]
+        L.orc_minimize_trace.argtypes = [OBJ_CB, C.c_void_p, D, D, C.c_int, C.c_int, D, D, D, D,
+                                         I32, I32]
         L.orc_lockstep.argtypes = [C.c_void_p, C.c_void_p, D, D, D, C.c_int, C.c_int, D, D, D, D,
                                    D, C.c_double, D]
         L.orc_results.argtypes = [C.c_void_p, C.c_void_p, D, D, D, D, C.c_int, C.c_int, D, I32,
@@ -93,7 +99,8 @@ def _nullable(a):
 
 TERMS = ["world", "vel", "acc", "jerk", "goal_pos", "goal_rot", "limit", "self"]
 RESULT_FIELDS = ["J", "clearance", "pos_err", "rot_err", "max_jerk", "collision_free",
-                 "within_limits", "success", "valid"]
+                 "within_limits", "success", "valid", "max_vel", "max_acc", "motion_time",
+                 "within_vel"]
 
 
 class RobotH:
@@ -243,7 +250,7 @@ class Oracle:
         S, T, _ = X.shape
         qs, qsp = _d(qs)
         goal, gp = _d(goal)
-        out = np.zeros((S, 9))
+        out = np.zeros((S, len(RESULT_FIELDS)))
         best = np.zeros(2, dtype=np.int32)
         lib().orc_results(self.robot.h, self.grid.h, self._pp, qsp, gp, xp, S, T,
                           out.ctypes.data_as(D), best.ctypes.data_as(I32), self.threads)
@@ -272,6 +279,54 @@ def minimize(f, x0, iters, params_list):
     lib().orc_minimize(cfunc, None, pp.ctypes.data_as(D), x0.ctypes.data_as(D), n, iters,
                        xo.ctypes.data_as(D), Jt.ctypes.data_as(D))
     return xo, Jt
+
+
+def choose_step(J0, gtd, Jk, params_list):
+    """Line-search choice for candidate costs Jk (alpha_k = 2^-k): returns
+    (index or -1, decision margin)."""
+    Jk, jp = _d(Jk)
+    pp, ppp = _d(params_list)
+    m = C.c_double()
+    k = lib().orc_choose_step(ppp, float(J0), float(gtd), jp, Jk.shape[0], C.byref(m))
+    return k, m.value
+
+
+def direction(g, S_hist, Y_hist, params_list):
+    """The optimiser's search direction (restart and cap included) for
+    history pairs [count][n], oldest first: returns (d, history cleared)."""
+    g, gp = _d(g)
+    n = g.shape[0]
+    S_hist, sp = _d(np.asarray(S_hist, dtype=np.float64).reshape(-1, n))
+    Y_hist, yp = _d(np.asarray(Y_hist, dtype=np.float64).reshape(-1, n))
+    pp, ppp = _d(params_list)
+    d = np.zeros(n)
+    cl = lib().orc_direction(ppp, gp, sp, yp, S_hist.shape[0], n, d.ctypes.data_as(D))
+    return d, bool(cl)
+
+
+def minimize_trace(f, x0, iters, params_list):
+    """The oracle's L-BFGS on f(x) -> (J, g) with a per-iteration record:
+    dict(x, g [iters+1, n], d [iters, n], alpha, pushed, count [iters])."""
+    x0 = np.ascontiguousarray(x0, dtype=np.float64)
+    n = x0.shape[0]
+
+    def cb(xp, gp, _user):
+        x = np.ctypeslib.as_array(xp, shape=(n,)).copy()
+        J, g = f(x)
+        if gp:
+            np.ctypeslib.as_array(gp, shape=(n,))[:] = g
+        return float(J)
+
+    cfunc = OBJ_CB(cb)
+    pp = np.ascontiguousarray(params_list, dtype=np.float64)
+    out = {"x": np.zeros((iters + 1, n)), "g": np.zeros((iters + 1, n)),
+           "d": np.zeros((iters, n)), "alpha": np.zeros(iters),
+           "pushed": np.zeros(iters, dtype=np.int32), "count": np.zeros(iters, dtype=np.int32)}
+    lib().orc_minimize_trace(cfunc, None, pp.ctypes.data_as(D), x0.ctypes.data_as(D), n, iters,
+                             out["x"].ctypes.data_as(D), out["g"].ctypes.data_as(D),
+                             out["d"].ctypes.data_as(D), out["alpha"].ctypes.data_as(D),
+                             out["pushed"].ctypes.data_as(I32), out["count"].ctypes.data_as(I32))
+    return out
 
 
 def two_loop(g, S_hist, Y_hist):

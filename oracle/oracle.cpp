@@ -7,9 +7,10 @@
 // trajectory tau = (q_0 .. q_{T-1}) of a 7-joint arm, minimise
 //     C_goal(X_d, FK(q_{T-1})) + C_smooth(tau) + C_world(tau)
 // subject to joint limits, for a fixed number of iterations, starting from
-// the given seeds (Sec. 4.4).  Self-collision (C_self) is not part of this
-// path.  The paper names the terms only; the concrete forms below are the
-// readings listed in the design notes:
+// the given seeds (Sec. 4.4), plus the optional self-collision term C_self
+// (off unless its weight is set) and optional swept sub-samples between
+// waypoints.  The paper names the terms only; the concrete forms below are
+// the readings listed in the design notes:
 //   * kinematics: T_i = T_{i-1} F_i Rz(q_i), spheres fixed in link frames;
 //   * C_world: CHOMP smooth hinge of (trilinear ESDF distance - radius);
 //   * C_smooth: squared 1st/2nd/3rd finite differences of the trajectory
@@ -23,7 +24,10 @@
 // Parity pins (tests/test_oracle_*.py): FK invariants, analytic box
 // distances, closed-form smoothness on polynomial trajectories,
 // quaternion identities, central finite differences, dense BFGS
-// recursion, quadratic / Rosenbrock convergence.
+// recursion, quadratic / Rosenbrock convergence, hand-worked line-search
+// choices, the restart / step / cap of the direction, history eviction,
+// closed-form trajectory metrics and the one-sided gradient jump that the
+// ambiguity bound covers.
 
 #include <algorithm>
 #include <cmath>
@@ -64,6 +68,7 @@ struct Params {
   double c1, delta0, dmax, dt, tol_pos, tol_rot;
   double ws;   // self-collision weight (0: the term is off)
   int nsub;    // swept sub-samples per segment (0: waypoints only)
+  double vlim, alim, jlim;   // joint velocity / acceleration / jerk limits (motion time)
 };
 
 struct Problem {
@@ -692,6 +697,8 @@ struct TrajObjective {
 struct SeedResult {
   double J, clearance, pos_err, rot_err, max_jerk;
   int collision_free, within_limits, success, valid;
+  double max_vel, max_acc, motion_time;
+  int within_vel;
 };
 
 SeedResult results(const Robot& rb, const Grid& G, const Params& P, const Problem& pr,
@@ -763,14 +770,36 @@ SeedResult results(const Robot& rb, const Grid& G, const Params& P, const Proble
     }
   R.success = (R.valid && R.collision_free && R.pos_err < P.tol_pos && R.rot_err < P.tol_rot &&
                R.within_limits) ? 1 : 0;
-  double mj = 0;
+  // App. A.7 trajectory metrics from the waypoints spaced dt apart: the
+  // largest first, second and third difference over all joints (velocity,
+  // acceleration, jerk), and the motion time of the trajectory slowed down
+  // uniformly just enough to respect the velocity, acceleration and jerk
+  // limits (a time scale s divides them by s, s^2 and s^3).
+  double mv = 0, ma = 0, mj = 0;
+  for (int t = 0; t + 1 < T; ++t)
+    for (int j = 0; j < NJ; ++j) {
+      double r = X[(size_t)(t + 1) * NJ + j] - X[(size_t)t * NJ + j];
+      mv = std::max(mv, std::fabs(r));
+    }
+  for (int t = 0; t + 2 < T; ++t)
+    for (int j = 0; j < NJ; ++j) {
+      double r = X[(size_t)(t + 2) * NJ + j] - 2 * X[(size_t)(t + 1) * NJ + j] +
+                 X[(size_t)t * NJ + j];
+      ma = std::max(ma, std::fabs(r));
+    }
   for (int t = 0; t + 3 < T; ++t)
     for (int j = 0; j < NJ; ++j) {
       double r = X[(size_t)(t + 3) * NJ + j] - 3 * X[(size_t)(t + 2) * NJ + j] +
                  3 * X[(size_t)(t + 1) * NJ + j] - X[(size_t)t * NJ + j];
       mj = std::max(mj, std::fabs(r));
     }
+  R.max_vel = mv / P.dt;
+  R.max_acc = ma / (P.dt * P.dt);
   R.max_jerk = mj / (P.dt * P.dt * P.dt);
+  R.within_vel = R.max_vel <= P.vlim ? 1 : 0;
+  double scale = std::max({1.0, R.max_vel / P.vlim, std::sqrt(R.max_acc / P.alim),
+                           std::cbrt(R.max_jerk / P.jlim)});
+  R.motion_time = scale * (T - 1) * P.dt;
   return R;
 }
 
@@ -793,6 +822,7 @@ Params make_params(const double* p) {
   P.tol_pos = p[14]; P.tol_rot = p[15];
   P.ws = p[16];
   P.nsub = (int)p[17];
+  P.vlim = p[18]; P.alim = p[19]; P.jlim = p[20];
   return P;
 }
 
@@ -976,6 +1006,56 @@ void orc_two_loop(const double* g, const double* S_hist, const double* Y_hist, i
   direction(P, H, g, n, d);
 }
 
+// Line-search choice for given candidate costs Jk[K] (alpha_k = 2^-k) at
+// cost J0 with directional derivative gtd; margin receives the decision
+// margin.  Returns the chosen candidate or -1 (no step).
+int orc_choose_step(const double* params, double J0, double gtd, const double* Jk, int K,
+                    double* margin) {
+  Params P = make_params(params);
+  return choose_step(P, J0, gtd, Jk, K, margin);
+}
+
+// Search direction with the restart and the cap of the optimiser
+// (direction()) for gradient g and history pairs S_hist/Y_hist [count][n]
+// (oldest first, rho = 1/s.y).  Returns 1 when the history was cleared.
+int orc_direction(const double* params, const double* g, const double* S_hist,
+                  const double* Y_hist, int count, int n, double* d) {
+  Params P = make_params(params);
+  History H;
+  for (int k = 0; k < count; ++k) {
+    Pair p;
+    p.s.assign(S_hist + (size_t)k * n, S_hist + (size_t)(k + 1) * n);
+    p.y.assign(Y_hist + (size_t)k * n, Y_hist + (size_t)(k + 1) * n);
+    p.rho = 1.0 / dot(p.s.data(), p.y.data(), n);
+    H.pairs.push_back(p);
+  }
+  return direction(P, H, g, n, d) ? 1 : 0;
+}
+
+// The generic minimiser with a per-iteration record: x_trace, g_trace
+// [iters+1][n] (iterate and gradient before each step), d_trace [iters][n]
+// (search direction), alpha_trace [iters], pushed [iters] (1 when the pair
+// entered the history), hist_count [iters] (history size after the step).
+void orc_minimize_trace(orc_objective_cb cb, void* user, const double* params, const double* x0,
+                        int n, int iters, double* x_trace, double* g_trace, double* d_trace,
+                        double* alpha_trace, int* pushed, int* hist_count) {
+  Params P = make_params(params);
+  Objective f = [cb, user](const double* x, double* g) { return cb(x, g, user); };
+  std::vector<double> x(x0, x0 + n), g(n);
+  double J = f(x.data(), g.data());
+  History H;
+  for (int k = 0; k < iters; ++k) {
+    std::copy(x.begin(), x.end(), x_trace + (size_t)k * n);
+    std::copy(g.begin(), g.end(), g_trace + (size_t)k * n);
+    StepInfo si = step(P, f, x, g, J, H, d_trace + (size_t)k * n, nullptr);
+    alpha_trace[k] = si.alpha;
+    pushed[k] = si.pushed ? 1 : 0;
+    hist_count[k] = (int)H.pairs.size();
+  }
+  std::copy(x.begin(), x.end(), x_trace + (size_t)iters * n);
+  std::copy(g.begin(), g.end(), g_trace + (size_t)iters * n);
+}
+
 // Lockstep replay of a traced GPU run of one seed.  Inputs are the GPU's
 // per-iteration iterates x_k [iters+1][T][7], gradients g_k, costs J_k,
 // directions d_k [iters][T][7] and accepted steps alpha_k [iters].
@@ -1066,8 +1146,9 @@ void orc_lockstep(void* rbp, void* gp, const double* params, const double* qs, c
   }
 }
 
-// Per-seed results for X[S][T][7]: out[S][9] = J, clearance, pos_err,
-// rot_err, max_jerk, collision_free, within_limits, success, valid.
+// Per-seed results for X[S][T][7]: out[S][13] = J, clearance, pos_err,
+// rot_err, max_jerk, collision_free, within_limits, success, valid,
+// max_vel, max_acc, motion_time, within_vel.
 // best[2] = best seed index (-1 if none valid), any-success flag.
 void orc_results(void* rb, void* g, const double* params, const double* qs, const double* goal,
                  const double* X, int S, int T, double* out, int* best, int nthreads) {
@@ -1087,10 +1168,11 @@ void orc_results(void* rb, void* g, const double* params, const double* qs, cons
     if (b < 0 || r.J < res[b].J) b = s;
   }
   for (int s = 0; s < S; ++s) {
-    double* o = out + (size_t)s * 9;
+    double* o = out + (size_t)s * 13;
     const SeedResult& r = res[s];
     o[0] = r.J; o[1] = r.clearance; o[2] = r.pos_err; o[3] = r.rot_err; o[4] = r.max_jerk;
     o[5] = r.collision_free; o[6] = r.within_limits; o[7] = r.success; o[8] = r.valid;
+    o[9] = r.max_vel; o[10] = r.max_acc; o[11] = r.motion_time; o[12] = r.within_vel;
   }
   best[0] = b;
   best[1] = any;

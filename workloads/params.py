@@ -22,11 +22,14 @@ DEFAULT = {
     "tol_rot": 2.86 * math.pi / 180.0,   # success threshold delta_r [rad]
     "w_self": 0.0,             # self-collision weight (0: term off)
     "swept_samples": 0,        # interpolated configurations per segment (0: waypoints only)
+    "v_limit": 2.5,            # joint velocity limit [rad/s] (motion-time metric)
+    "a_limit": 10.0,           # joint acceleration limit [rad/s^2]
+    "j_limit": 5000.0,         # joint jerk limit [rad/s^3]
 }
 
 ORDER = ["w_collision", "eps", "lambda_v", "lambda_a", "lambda_j", "w_pos", "w_rot",
          "w_limit", "history", "n_ls", "c1", "delta0", "step_max", "dt", "tol_pos", "tol_rot",
-         "w_self", "swept_samples"]
+         "w_self", "swept_samples", "v_limit", "a_limit", "j_limit"]
 
 
 def as_list(p=None):
