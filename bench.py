@@ -2,15 +2,19 @@
 """Benchmark of the seeded trajectory optimiser on one MI355X.
 
 A step is one pass of the whole hot path over one batch of synthetic input:
-upload-free optimisation of every seed of the batch for N_iters L-BFGS
-iterations (FK, spheres, ESDF gathers, costs, adjoint, line search, flags,
-best seed) plus reading back the best trajectory.  Inputs are resident in
-HBM before the timed region.
+optimisation of every seed of every problem of the batch for N_iters
+L-BFGS iterations (FK, spheres, ESDF gathers, costs, adjoint, line search,
+flags, best seed) plus reading back every problem's best trajectory.
+Inputs are resident in HBM before the timed region.
 
-Default workload (the single-GPU headline configuration): one cluttered
-shelf problem, 32 seeds x 32 waypoints, 56 spheres, 200^3 FP32 ESDF at 1 cm,
-100 iterations.  Extra fields report the batched-uneven workload (64
-problems, one persistent launch vs one launch per problem) and serving.
+Headline workload (the largest single-GPU configuration): the batched-uneven
+set -- 64 problems, seeds U{4..128}, horizons U{16..64}, 56 spheres, a 128^3
+FP32 ESDF at 1.5 cm per problem, 100 iterations -- in one persistent
+launch.  Extra fields: the same set as one launch per problem (the plain
+form), the cluttered single problem (32 x 32, 200^3, wavefront teams), the
+differentiation workload, serving at the workload's rate and a rate sweep
+for the largest rate with p99 <= 100 ms, the GPU distance-field build, and
+the FP64 oracle on the host cores.
 
 Prints one JSON line on stdout; progress goes to stderr.
 """
@@ -26,9 +30,12 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
+# VALU issue ceiling: 256 CUs x 4 SIMDs x 2.4 GHz, one wave64 VALU
+# instruction per SIMD every 4 cycles (16 lanes per SIMD)
+VALU_PEAK_GIPS = 256 * 4 * 2.4e9 / 4 / 1e9
 KERNEL_SOURCES = ["paper_2410_16727_amd/csrc/dsopt_kernels.hip",
                   "paper_2410_16727_amd/csrc/dsopt_internal.h"]
-PMC_SUMMARY = "profiles/k_optimize_pmc_cluttered.json"
+PMC_SUMMARY = "profiles/k_optimize_pmc_batched.json"
 COPY_BYTES = 256 << 20
 
 
@@ -41,18 +48,19 @@ def kernel_source_hash():
     return h.hexdigest()
 
 
-def measured_traffic():
-    """HBM bytes per optimiser launch from the committed rocprofv3 PMC
-    summary (FETCH_SIZE + WRITE_SIZE, scaled by the copy-kernel factors),
-    or None when the kernel source changed since the counters were taken."""
+def measured_counters():
+    """The committed rocprofv3 PMC summary of the batched launch (HBM bytes
+    per launch from FETCH_SIZE + WRITE_SIZE scaled by the copy-kernel
+    factors, VALU instructions per launch), or None when the kernel source
+    changed since the counters were taken."""
     path = os.path.join(ROOT, PMC_SUMMARY)
     if not os.path.exists(path):
-        return None, None
+        return None
     with open(path) as f:
         rec = json.load(f)
     if rec.get("kernel_source_sha256") != kernel_source_hash():
-        return None, rec
-    return rec.get("traffic_bytes_per_launch"), rec
+        return None
+    return rec
 
 
 def log(*a):
@@ -76,15 +84,27 @@ def evals_per_seed(res):
     return res["n_evals_grad"] + res["n_evals_cost"] + 1
 
 
+def hinge_active_fraction(plan, scene, robot, X, eps):
+    """Fraction of the sphere samples of trajectories X [S, T, 7] (cuda)
+    within the hinge's activation distance of an obstacle: centres from the
+    library's kinematics kernel, exact box distances from the scene's boxes
+    (a description of the workload, outside any timed region)."""
+    from workloads import gen
+    c = plan.sphere_centres(X).cpu().numpy().astype(np.float64)
+    d = gen.scene_sdf(c, scene) - robot.sphere_radius.astype(np.float64)
+    return float(np.mean(d < eps))
+
+
 def run_single(args, dsopt, torch, configs, params):
-    key = args.workload
+    """The cluttered single problem (32 seeds x 32 waypoints, 200^3 shelf
+    scene) with wavefront teams: the latency-bound form."""
+    key = "B"
     w = configs.WORKLOADS[key]
     robot = configs.robot(key)
     scene = configs.scenes(key, only={0})[0]
     prob = configs.problems(key)[0]
     S, T, N = prob.S, prob.T, w.iters
-    log(f"[bench] workload {key} ({w.name}): S={S} T={T} spheres={robot.n_spheres} "
-        f"grid={scene.dims} iters={N}")
+    log(f"[bench] cluttered: S={S} T={T} spheres={robot.n_spheres} grid={scene.dims} iters={N}")
     prm = dict(params.DEFAULT, waves_per_seed=args.waves)
     plan = dsopt.Plan(robot, prm, N, 1 << 30)
     plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
@@ -111,36 +131,47 @@ def run_single(args, dsopt, torch, configs, params):
         step()
     torch.cuda.synchronize()
     plan.kernel_timing(True)
+    steps = max(1, args.single_steps)
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         step()
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     plan.kernel_timing(False)
     k_ms, k_n = plan.kernel_timing_read()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    # algorithmic bytes: 32 B of cell corners per sphere sample of every
-    # evaluation; the bytes the kernel actually gathered (its own per-seed
-    # counters x 32 B) are fewer, the coarse-table skip proves the rest zero
+    ms_step = (t1 - t0) * 1e3 / steps
     sample_bytes = float(np.sum(n_evals)) * T * robot.n_spheres * 32.0
     gather_bytes = float(np.sum(sres["n_gathers"])) * 32.0
     avg_kernel_s = k_ms / max(k_n, 1) / 1e3
-    achieved = sample_bytes / avg_kernel_s / 1e9
-    log(f"[bench] {ms_step:.3f} ms/step, kernel {k_ms / max(k_n, 1):.3f} ms/launch, "
-        f"evals/seed {np.mean(n_evals):.1f}, gathered {gather_bytes / sample_bytes:.3f} of "
-        f"the samples, {achieved:.1f} GB/s, best {best}")
+    active = hinge_active_fraction(plan, scene, robot, seeds, params.DEFAULT["eps"])
+    log(f"[bench] cluttered: {ms_step:.3f} ms/step, kernel {k_ms / max(k_n, 1):.3f} ms/launch, "
+        f"hinge-active seed samples {active:.3f}, gathered {gather_bytes / sample_bytes:.3f} of "
+        f"the samples, best {best}")
     plan.close()
     return {
-        "S": S, "T": T, "N": N, "spheres": robot.n_spheres, "grid": list(scene.dims),
+        "workload": f"cluttered: 1 problem, {S} seeds x {T} waypoints, {robot.n_spheres} spheres, "
+                    f"{scene.dims[0]}^3 FP32 ESDF at 1 cm (shelf, 20 boxes), {N} L-BFGS iters, "
+                    f"{args.waves} wavefronts per seed",
         "ms_per_step": ms_step, "kernel_ms": k_ms / max(k_n, 1),
-        "gather_bytes": gather_bytes, "sample_bytes": sample_bytes, "achieved_gbs": achieved,
-        "evals_per_seed": float(np.mean(n_evals)), "best": best,
-        "scene": scene, "robot": robot, "prob": prob,
+        "seed_waypoint_evals_per_s": S * T * N / (ms_step / 1e3),
+        "problems_per_s": 1e3 / ms_step,
+        "seed_hinge_active_fraction": active,
+        "algorithmic_bytes_per_launch": sample_bytes,
+        "achieved_algorithmic_gbs": sample_bytes / avg_kernel_s / 1e9,
+        "gathered_bytes_per_launch": gather_bytes,
+        "gathered_frac_of_samples": gather_bytes / sample_bytes,
+        "evals_per_seed": float(np.mean(n_evals)),
+        "best_seed": {k: best[k] for k in ("best_seed", "success", "collision_free", "cost",
+                                           "min_clearance_m", "pos_err_m", "rot_err_rad",
+                                           "max_jerk", "motion_time")},
+        "_scene": scene, "_robot": robot, "_prob": prob,
     }
 
 
 def run_batched(args, dsopt, torch, configs, params):
-    """64 uneven problems: one persistent launch vs one launch per problem."""
+    """The headline: 64 uneven problems in one persistent launch per step
+    (args.steps timed steps after args.warmup), and the plain form (one
+    launch per problem) beside it."""
     key = "D"
     w = configs.WORKLOADS[key]
     robot = configs.robot(key)
@@ -150,9 +181,7 @@ def run_batched(args, dsopt, torch, configs, params):
     probs = configs.problems(key)
     N = w.iters
     cells = sum((s.dims[0] - 1) * (s.dims[1] - 1) * (s.dims[2] - 1) for s in scenes)
-    per = lambda T: 64 // (16 if T <= 16 else 32 if T <= 32 else 64)
-    state = sum(((p.S + per(p.T) - 1) // per(p.T)) * 40 * 1024 + p.S * p.T * 28 + p.S * 64
-                for p in probs)
+    state = sum(p.S * 40 * 1024 + p.S * p.T * 28 + p.S * 64 for p in probs)
     arena = cells * 32 + 2 * state + (512 << 20)
     plan = dsopt.Plan(robot, dict(params.DEFAULT, waves_per_seed=args.batched_waves), N, arena)
     for i, sc in enumerate(scenes):
@@ -183,23 +212,29 @@ def run_batched(args, dsopt, torch, configs, params):
         for i in range(len(specs)):
             plan.release(base + i)
 
-    # evaluation counts of every seed (deterministic): algorithmic gather bytes
+    # evaluation and gather counts of every seed (deterministic)
     base = tagc[0]
     tagc[0] += len(specs)
     plan.optimize([dict(s, tag=base + i) for i, s in enumerate(specs)])
     gbytes = sbytes = 0.0
+    n_success = 0
     for i, p in enumerate(probs):
         r = plan.seed_results(base + i, p.S)
         gbytes += float(np.sum(r["n_gathers"])) * 32.0
         sbytes += float(np.sum(evals_per_seed(r))) * p.T * robot.n_spheres * 32.0
+        n_success += int(plan.get_best(base + i, p.T)[1]["success"])
         plan.release(base + i)
     out = {}
-    for name, fn in [("batched", batched), ("plain", plain)]:
-        fn()
+    legs = [("batched", batched, args.steps, args.warmup)]
+    if args.plain_steps > 0:
+        legs.append(("plain", plain, args.plain_steps, 1))
+    for name, fn, steps, warm in legs:
+        for _ in range(warm):
+            fn()
         torch.cuda.synchronize()
         plan.kernel_timing(True)
         t0 = time.perf_counter()
-        reps = max(1, args.batched_steps)
+        reps = max(1, steps)
         for _ in range(reps):
             fn()
         torch.cuda.synchronize()
@@ -210,19 +245,20 @@ def run_batched(args, dsopt, torch, configs, params):
                      "seed_waypoint_evals_per_s": sw * N / dt,
                      "problems_per_s": len(probs) / dt,
                      "kernel_ms_per_launch": k_ms / max(k_n, 1),
-                     "launches_per_batch": k_n / reps}
-        log(f"[bench] batched-uneven {name}: {dt * 1e3:.2f} ms/batch, "
-            f"{sw * N / dt:.3e} seed-waypoint evals/s")
+                     "launches_per_batch": k_n / reps, "steps": reps}
+        log(f"[bench] batched-uneven {name}: {dt * 1e3:.2f} ms/batch, kernel "
+            f"{k_ms / max(k_n, 1):.3f} ms/launch, {sw * N / dt:.3e} seed-waypoint evals/s")
     plan.close()
-    kb = out["batched"]["kernel_ms_per_launch"] / 1e3
-    out["roofline"] = {"bound": "hbm", "kernel": "k_optimize (one persistent launch)",
-                       "achieved": sbytes / kb / 1e9, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                       "frac": sbytes / kb / 1e9 / HBM_PEAK_GBS,
-                       "algorithmic_bytes_per_launch": sbytes,
-                       "gathered_bytes_per_launch": gbytes, "gathered_frac": gbytes / sbytes}
-    out["speedup_batched_vs_plain"] = out["plain"]["ms_per_batch"] / out["batched"]["ms_per_batch"]
+    out["sw"] = sw
+    out["N"] = N
+    out["n_problems"] = len(probs)
+    out["algorithmic_bytes_per_launch"] = sbytes
+    out["gathered_bytes_per_launch"] = gbytes
+    out["problems_successful"] = n_success
     out["workload"] = (f"batched-uneven: {len(probs)} problems, seeds U{{4..128}}, horizons "
-                       f"U{{16..64}}, {sw} seed-waypoints, 128^3 ESDF per problem, {N} iters")
+                       f"U{{16..64}}, {sw} seed-waypoints, {robot.n_spheres} spheres, a 128^3 FP32 "
+                       f"ESDF at 1.5 cm per problem (5-30 random boxes), {N} L-BFGS iters, one "
+                       f"persistent launch")
     return out
 
 
@@ -320,13 +356,11 @@ def run_serving(args, dsopt, torch, configs, params):
     # plain serial form: on a plan with its own best (latency) team size
     pp = make_plan(args.serve_plain_waves, 10)
     out = {}
-    for tag, n, rate in (("rate", args.serve_requests, args.serve_rate),
-                         ("saturated", args.serve_sat_requests, args.serve_sat_rate)):
-        if n <= 0:
-            continue
+    if args.serve_requests > 0:
+        n, rate = args.serve_requests, args.serve_rate
         reqs = make_reqs(n, rate)
         warm = min(200, n // 10)
-        out[tag] = {
+        out["rate"] = {
             "workload": (f"serving: Poisson {n} requests at {rate:g}/s ({warm} warm-up), "
                          f"seeds U{{8..128}}, horizons U{{32..64}}, 16 resident 200^3 ESDFs, "
                          f"{N} iters, blocks of {args.serve_block} iterations per graph replay, "
@@ -336,6 +370,35 @@ def run_serving(args, dsopt, torch, configs, params):
             "served": served(sp, reqs, warm, f"served @{rate:g}/s"),
             "plain_serial": plain(pp, reqs, warm, f"plain serial @{rate:g}/s")}
         del reqs
+    # the largest sustainable rate: open-loop Poisson arrivals at rising
+    # rates until p99 exceeds the latency bound or the completion rate falls
+    # below 95 % of the arrival rate
+    if args.sweep_requests > 0:
+        sweep = {}
+        for name, plan, fn, rates in (
+                ("served", sp, served, [float(r) for r in args.sweep_rates_served.split(",")]),
+                ("plain_serial", pp, plain, [float(r) for r in args.sweep_rates_plain.split(",")])):
+            pts = []
+            best = 0.0
+            for rate in rates:
+                reqs = make_reqs(args.sweep_requests, rate)
+                warm = args.sweep_requests // 10
+                r = fn(plan, reqs, warm, f"{name} sweep @{rate:g}/s")
+                del reqs
+                ok = r["p99_ms"] <= args.p99_bound_ms and r["problems_per_s"] >= 0.95 * rate
+                pts.append({"rate": rate, "p50_ms": r["p50_ms"], "p99_ms": r["p99_ms"],
+                            "problems_per_s": r["problems_per_s"], "sustained": ok})
+                if ok:
+                    best = rate
+                else:
+                    break
+            sweep[name] = {"points": pts, "max_sustainable_rate": best}
+            log(f"[bench] sweep {name}: max sustainable rate {best:g}/s "
+                f"(p99 <= {args.p99_bound_ms:g} ms)")
+        sweep["workload"] = (f"open-loop Poisson arrivals, {args.sweep_requests} requests per rate "
+                             f"(10 % warm-up), same request mix; a rate is sustained when p99 <= "
+                             f"{args.p99_bound_ms:g} ms and the completion rate is >= 95 % of it")
+        out["max_rate_sweep"] = sweep
     sp.close()
     pp.close()
     return out
@@ -343,10 +406,11 @@ def run_serving(args, dsopt, torch, configs, params):
 
 def run_differentiation(args, dsopt, torch, configs, params):
     """Cost + gradient of 256 seeds x 64 waypoints (60 spheres, 200^3) in
-    one call, and the same through the autograd function (forward: cost and
-    adjoint gradient in one launch, kinematics recomputed; backward: the
-    saved gradient scaled by dJ), timed with events on the stream both run
-    on."""
+    one call, and the same through the autograd function (forward: the cost
+    kernel; backward: the adjoint kernel with dJ, kinematics recomputed),
+    and in its fused form (one cost+gradient launch in forward, the saved
+    gradient scaled by dJ in backward), timed with events on the stream all
+    run on."""
     from paper_2410_16727_amd.autograd import trajectory_cost
     key = "C"
     robot = configs.robot(key)
@@ -377,16 +441,21 @@ def run_differentiation(args, dsopt, torch, configs, params):
         Xr = X.clone().requires_grad_(True)
         trajectory_cost(Xr, plan, 0, prob.q_start, prob.goal).sum().backward()
 
+    def fwd_bwd_fused():
+        Xr = X.clone().requires_grad_(True)
+        trajectory_cost(Xr, plan, 0, prob.q_start, prob.goal, fused=True).sum().backward()
+
     ms_ag = timed(fwd_bwd)
+    ms_agf = timed(fwd_bwd_fused)
     plan.close()
     sample_bytes = float(S * T * robot.n_spheres * 32)
     achieved = sample_bytes / (ms_cg * 1e-3) / 1e9
     log(f"[bench] differentiation: cost+grad {ms_cg:.3f} ms ({S * T / (ms_cg * 1e-3):.3e} "
-        f"seed-waypoint evals/s), autograd forward+backward {ms_ag:.3f} ms")
+        f"seed-waypoint evals/s), autograd forward+backward {ms_ag:.3f} ms (fused {ms_agf:.3f} ms)")
     return {"workload": f"differentiation: {S} seeds x {T} waypoints, {robot.n_spheres} spheres, "
                         f"{scene.dims[0]}^3 ESDF, one cost+gradient call",
             "cost_grad_ms": ms_cg, "seed_waypoint_evals_per_s": S * T / (ms_cg * 1e-3),
-            "autograd_fwd_bwd_ms": ms_ag,
+            "autograd_fwd_bwd_ms": ms_ag, "autograd_fused_fwd_bwd_ms": ms_agf,
             "roofline": {"bound": "hbm", "kernel": "k_cost (cost+gradient)", "achieved": achieved,
                          "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                          "algorithmic_bytes_per_launch": sample_bytes}}
@@ -412,58 +481,114 @@ def run_esdf_build(args, dsopt, torch, configs, params, scene):
             "what": "signed EDT of the occupancy grid + packing into gather records"}
 
 
-def cpu_baseline(single, params, configs):
-    """The FP64 oracle on the same problem, all host threads, ~10 s."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_rate(key, configs, params, threads, budget_s, max_problems=None, max_seeds=None):
+    """The FP64 oracle's free-running optimisation over the workload's
+    problems in order (first max_seeds seeds of each), until budget_s of
+    wall time is spent (at least one problem): seed-waypoint evals/s and
+    what was timed."""
     import oracle
-    key = "B"
-    robot, scene, prob = single["robot"], single["scene"], single["prob"]
-    N = single["N"]
-    threads = host_threads()
-    O = oracle.Oracle(robot, scene, params.as_list(), threads=threads)
-    X0 = configs.seeds_for(key, 0, prob).astype(np.float64)
-    reps = 0
-    t0 = time.perf_counter()
-    while True:
-        O.optimize(prob.q_start, prob.goal, X0, N)
-        reps += 1
-        el = time.perf_counter() - t0
-        if el > 10.0 or reps >= 200:
+    w = configs.WORKLOADS[key]
+    robot = configs.robot(key)
+    probs = configs.problems(key)
+    if max_problems:
+        probs = probs[:max_problems]
+    work = 0
+    el = 0.0
+    done = 0
+    cache = {}
+    for i, p in enumerate(probs):
+        if p.scene not in cache:
+            cache = {p.scene: configs.scenes(key, only={p.scene}, threads=threads)[p.scene]}
+        O = oracle.Oracle(robot, cache[p.scene], params.as_list(), threads=threads)
+        X0 = configs.seeds_for(key, i, p).astype(np.float64)
+        if max_seeds:
+            X0 = X0[:max_seeds]
+        t0 = time.perf_counter()
+        O.optimize(p.q_start, p.goal, X0, w.iters)
+        el += time.perf_counter() - t0
+        work += X0.shape[0] * X0.shape[1] * w.iters
+        done += 1
+        if el >= budget_s:
             break
-    S, T = X0.shape[0], X0.shape[1]
-    val = reps * S * T * N / el
-    log(f"[bench] cpu oracle: {reps} runs in {el:.1f} s on {threads} threads -> {val:.3e} evals/s")
+    return work / el, f"{done} problem(s){'' if not max_seeds else f' (first {max_seeds} seeds each)'}, {work} seed-waypoint iterations in {el:.1f} s"
+
+
+def cpu_baseline(args, configs, params):
+    """The oracle as it stands on the headline workload (batched-uneven),
+    all host threads, a bounded sample (problems in order until ~10 s)."""
+    threads = host_threads()
+    val, what = cpu_rate("D", configs, params, threads, args.cpu_seconds)
+    log(f"[bench] cpu oracle (batched-uneven, {threads} threads): {val:.3e} evals/s, {what}")
     return {"value": val, "unit": "seed-waypoint evals/s", "cores": threads, "kind": "oracle",
-            "sample": f"cluttered problem ({S} seeds x {T} waypoints x {N} iterations, FP64 "
-                      f"oracle, OpenMP over seeds) repeated {reps} times"}
+            "sample": f"batched-uneven workload: {what}; FP64 oracle, OpenMP over seeds, "
+                      f"100 iterations per problem",
+            "cpu_model": cpu_model(), "nproc": os.cpu_count()}
+
+
+def cpu_detail(args, configs, params):
+    """The oracle single-threaded and on all host threads for the tiny,
+    cluttered, differentiation and batched-uneven workloads (the last two
+    on the first 16 seeds of each problem), each on a short bounded
+    sample."""
+    threads = host_threads()
+    out = {"cpu_model": cpu_model(), "nproc": os.cpu_count(), "threads_all": threads}
+    for key, kw in (("A", {}), ("B", {}), ("C", {"max_seeds": 16}), ("D", {"max_seeds": 16})):
+        row = {}
+        for label, th in (("single_thread", 1), ("all_threads", threads)):
+            val, what = cpu_rate(key, configs, params, th, args.cpu_detail_seconds, **kw)
+            row[label] = {"seed_waypoint_evals_per_s": val, "sample": what}
+        out[configs.WORKLOADS[key].name] = row
+        log(f"[bench] cpu oracle {key}: 1 thread {row['single_thread']['seed_waypoint_evals_per_s']:.3e}, "
+            f"{threads} threads {row['all_threads']['seed_waypoint_evals_per_s']:.3e} evals/s")
+    return out
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--steps", type=int, default=20,
+                    help="timed steps (batches) of the headline workload")
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", default="B", choices=["A", "B", "C"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-cpu-detail", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-detail-seconds", type=float, default=1.5)
     ap.add_argument("--waves", type=int, default=8,
-                    help="wavefronts per seed for the single-problem workload")
+                    help="wavefronts per seed for the cluttered single problem")
     ap.add_argument("--batched-waves", type=int, default=1,
                     help="wavefronts per seed for the batched workload")
+    ap.add_argument("--plain-steps", type=int, default=2,
+                    help="timed batches of the one-launch-per-problem form")
+    ap.add_argument("--single-steps", type=int, default=20)
     ap.add_argument("--serve-waves", type=int, default=8,
                     help="wavefronts per seed for the served (batched) form")
     ap.add_argument("--serve-plain-waves", type=int, default=8,
                     help="wavefronts per seed for the plain serial form")
-    ap.add_argument("--no-batched", action="store_true")
-    ap.add_argument("--batched-steps", type=int, default=3)
+    ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--no-serving", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="headline only (profiling runs)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="run one 256 MiB device copy (known traffic) for PMC scaling")
     ap.add_argument("--serve-requests", type=int, default=2200)
     ap.add_argument("--serve-rate", type=float, default=200.0,
                     help="Poisson arrival rate of the serving workload [1/s]")
-    ap.add_argument("--serve-sat-requests", type=int, default=1000,
-                    help="requests of the saturated serving run (0: skip)")
-    ap.add_argument("--serve-sat-rate", type=float, default=2000.0,
-                    help="arrival rate of the saturated serving run [1/s]")
+    ap.add_argument("--sweep-requests", type=int, default=600,
+                    help="requests per rate of the sustainable-rate sweep (0: skip)")
+    ap.add_argument("--sweep-rates-served", default="500,1000,2000,3000,4000,6000,8000")
+    ap.add_argument("--sweep-rates-plain", default="200,400,600,800,1000,1200")
+    ap.add_argument("--p99-bound-ms", type=float, default=100.0)
     ap.add_argument("--serve-slots", type=int, default=64)
     ap.add_argument("--serve-block", type=int, default=25,
                     help="iterations per graph replay in the served form")
@@ -471,8 +596,8 @@ def main():
                     help="served form: run the active requests to completion when none waits")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (this path has no multi-GPU form); got "
-              f"--gpus {args.gpus}", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (this path has no multi-GPU form; the design "
+              f"notes describe how it would shard); got --gpus {args.gpus}", file=sys.stderr)
         sys.exit(2)
     import torch
 
@@ -489,47 +614,65 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-    single = run_single(args, dsopt, torch, configs, params)
-    traffic, pmc = measured_traffic()
-    S, T, N = single["S"], single["T"], single["N"]
-    value = S * T * N / (single["ms_per_step"] / 1e3)
+    bt = run_batched(args, dsopt, torch, configs, params)
+    sw, N = bt["sw"], bt["N"]
+    ms = bt["batched"]["ms_per_batch"]
+    kms = bt["batched"]["kernel_ms_per_launch"]
+    sbytes = bt["algorithmic_bytes_per_launch"]
+    gbytes = bt["gathered_bytes_per_launch"]
+    achieved = sbytes / (kms * 1e-3) / 1e9
+    pmc = measured_counters()
+    roof = {"bound": "hbm", "kernel": "k_optimize (one persistent launch, one wavefront per seed)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": pmc.get("traffic_bytes_per_launch") if pmc else None,
+            "kernel_ms": kms,
+            "algorithmic_bytes_per_launch": sbytes,
+            "gathered": {"bytes_per_launch": gbytes, "frac_of_samples": gbytes / sbytes,
+                         "achieved_gbs": gbytes / (kms * 1e-3) / 1e9,
+                         "frac_of_peak": gbytes / (kms * 1e-3) / 1e9 / HBM_PEAK_GBS},
+            "valu": None}
+    if pmc and pmc.get("valu_insts_per_launch"):
+        vi = pmc["valu_insts_per_launch"]
+        roof["valu"] = {"insts_per_launch": vi, "achieved_ginst_s": vi / (kms * 1e-3) / 1e9,
+                        "peak_ginst_s": VALU_PEAK_GIPS,
+                        "issue_frac": vi / (kms * 1e-3) / 1e9 / VALU_PEAK_GIPS}
     rec = {
         "metric": "seed-waypoint cost+grad evals/sec, problems/sec; p50/p99 plan latency vs plain",
-        "value": value,
+        "value": sw * N / (ms / 1e3),
         "unit": "seed-waypoint evals/s",
         "n_gpus": 1,
-        "steps": args.steps,
+        "steps": bt["batched"]["steps"],
         "warmup": args.warmup,
-        "ms_per_step": single["ms_per_step"],
+        "ms_per_step": ms,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32",
-        "data": "synthetic (seeded shelf scene and arm; no dataset)",
-        "config": {"workload": f"cluttered: 1 problem, {S} seeds x {T} waypoints, "
-                               f"{single['spheres']} spheres, {single['grid'][0]}^3 FP32 ESDF "
-                               f"at 1 cm, {N} L-BFGS iters",
-                   "seeds": S, "horizon": T, "iters": N, "spheres": single["spheres"],
-                   "waves_per_seed": args.waves},
-        "problems_per_s": 1e3 / single["ms_per_step"],
-        "roofline": {"bound": "hbm", "kernel": "k_optimize",
-                     "achieved": single["achieved_gbs"], "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": single["achieved_gbs"] / HBM_PEAK_GBS, "traffic": traffic,
-                     "kernel_ms": single["kernel_ms"],
-                     "algorithmic_bytes_per_launch": single["sample_bytes"],
-                     "gathered_bytes_per_launch": single["gather_bytes"],
-                     "gathered_frac": single["gather_bytes"] / single["sample_bytes"],
-                     "evals_per_seed": single["evals_per_seed"]},
+        "data": "synthetic (seeded random-box scenes, synthetic 7-joint arm; no dataset)",
+        "config": {"workload": bt["workload"], "problems": bt["n_problems"],
+                   "seed_waypoints": sw, "iters": N, "spheres": 56,
+                   "waves_per_seed": args.batched_waves},
+        "problems_per_s": bt["batched"]["problems_per_s"],
+        "roofline": roof,
+        "plain_form": (dict(bt["plain"], speedup_batched_vs_plain=bt["plain"]["ms_per_batch"] / ms)
+                       if "plain" in bt else None),
+        "problems_successful": bt["problems_successful"],
     }
-    rec["esdf_from_occupancy"] = run_esdf_build(args, dsopt, torch, configs, params,
-                                                single["scene"])
-    rec["differentiation"] = run_differentiation(args, dsopt, torch, configs, params)
-    if not args.no_batched:
-        rec["batched"] = run_batched(args, dsopt, torch, configs, params)
-    if not args.no_serving:
-        rec["serving"] = run_serving(args, dsopt, torch, configs, params)
+    if not args.no_extras:
+        single = None
+        if not args.no_single:
+            single = run_single(args, dsopt, torch, configs, params)
+            rec["esdf_from_occupancy"] = run_esdf_build(args, dsopt, torch, configs, params,
+                                                        single["_scene"])
+            rec["cluttered"] = {k: v for k, v in single.items() if not k.startswith("_")}
+        rec["differentiation"] = run_differentiation(args, dsopt, torch, configs, params)
+        if not args.no_serving:
+            rec["serving"] = run_serving(args, dsopt, torch, configs, params)
     if not args.no_cpu_baseline:
-        rec["cpu_baseline"] = cpu_baseline(single, params, configs)
+        rec["cpu_baseline"] = cpu_baseline(args, configs, params)
+        if not args.no_cpu_detail and not args.no_extras:
+            rec["cpu_detail"] = cpu_detail(args, configs, params)
     print(json.dumps(rec), flush=True)
 
 

@@ -52,7 +52,7 @@ extern "C" {
 #define DS_OK 0
 #define DS_ERR_INVALID (-1)   /* bad argument (shape, id, value) */
 #define DS_ERR_NOMEM (-2)     /* the caller's arena cannot hold the request */
-#define DS_ERR_BUSY (-3)      /* serving queue full */
+#define DS_ERR_BUSY (-3)      /* serving queue full, or a scene still in use */
 #define DS_ERR_NOT_FOUND (-4) /* unknown scene id / problem tag / ticket */
 #define DS_ERR_HIP (-5)       /* a HIP runtime call failed */
 #define DS_ERR_STATE (-6)     /* call not valid in the current state */
@@ -126,6 +126,9 @@ typedef struct ds_params {
                             waits, a replay runs the active requests to completion
                             (lower median latency at light load; a request that
                             arrives meanwhile waits for that replay). */
+  float v_limit;         /* joint velocity limit, rad/s, > 0 (App. A.7 motion time: */
+  float a_limit;         /* acceleration limit, rad/s^2, > 0  the trajectory slowed */
+  float j_limit;         /* jerk limit, rad/s^3, > 0          down to meet them) */
 } ds_params;
 
 /* One planning problem (Sec. 3).  `seeds` are the seed trajectories
@@ -155,9 +158,14 @@ typedef struct ds_result {
   float min_clearance_m;   /* min over waypoints and spheres of (distance - radius) */
   float max_jerk;          /* max |third difference| / dt^3 over waypoints and joints */
   int32_t n_iters;         /* iterations run */
+  float max_vel;           /* max |q_{t+1} - q_t| / dt over waypoints and joints */
+  float motion_time;       /* App. A.7: (T-1) dt times the smallest uniform slow-down
+                              s >= 1 that meets the limits: s = max(1, v/v_limit,
+                              sqrt(a/a_limit), cbrt(jerk/j_limit)) */
 } ds_result;
 
-/* Per-seed result (same fields as ds_result, for every seed). */
+/* Per-seed result (the fields of ds_result for every seed, plus the
+ * evaluation counters). */
 typedef struct ds_seed_result {
   float cost, clearance, pos_err, rot_err, max_jerk;
   int32_t collision_free, within_limits, success, valid;
@@ -166,6 +174,10 @@ typedef struct ds_seed_result {
   uint32_t n_gathers;      /* ESDF cell records (32 B each) gathered for this seed,
                               over all its wavefronts and launches; the coarse
                               table's skips are not counted */
+  float max_vel;           /* max |q_{t+1} - q_t| / dt */
+  float max_acc;           /* max |q_{t+2} - 2 q_{t+1} + q_t| / dt^2 */
+  float motion_time;       /* as in ds_result */
+  int32_t within_vel;      /* max_vel <= v_limit (reported; not part of success) */
 } ds_seed_result;
 
 typedef struct ds_plan ds_plan;
@@ -192,7 +204,11 @@ void ds_plan_destroy(ds_plan* plan);
  * its own gather layout (the 8 corners of every cell in one 32-byte record)
  * and keeps it resident until ds_esdf_release or destroy; re-uploading an
  * id replaces it.  Queries outside the grid are clamped to it.  Errors:
- * DS_ERR_INVALID (dims < 2, voxel <= 0, id < 0), DS_ERR_NOMEM. */
+ * DS_ERR_INVALID (dims < 2, voxel <= 0, id < 0, more than 2^26 - 1 cells, or
+ * (ny-1)*(nz-1) >= 2^24: cell indices are formed with 24-bit multiplies),
+ * DS_ERR_NOMEM, DS_ERR_BUSY (replacing a scene that a serving request
+ * still uses).  Releasing waits for all work on the device; it fails with
+ * DS_ERR_BUSY while a queued or admitted serving request uses the scene. */
 int ds_esdf_upload(ds_plan* plan, int32_t scene_id, const float* vals, int nx, int ny, int nz,
                    float voxel, const float origin[3], void* stream);
 int ds_esdf_release(ds_plan* plan, int32_t scene_id);

@@ -69,7 +69,10 @@ def lib():
         L.orc_minimize_trace.argtypes = [OBJ_CB, C.c_void_p, D, D, C.c_int, C.c_int, D, D, D, D,
                                          I32, I32]
         L.orc_lockstep.argtypes = [C.c_void_p, C.c_void_p, D, D, D, C.c_int, C.c_int, D, D, D, D,
-                                   D, C.c_double, D]
+                                   D, C.c_double, C.c_double, C.c_double, C.c_double, D]
+        L.orc_fp32_bound.restype = C.c_double
+        L.orc_fp32_bound.argtypes = [C.c_void_p, C.c_void_p, D, D, D, D, C.c_int, C.c_double,
+                                     C.c_double, D]
         L.orc_results.argtypes = [C.c_void_p, C.c_void_p, D, D, D, D, C.c_int, C.c_int, D, I32,
                                   C.c_int]
         L.orc_esdf_from_occupancy.restype = C.c_int
@@ -218,9 +221,23 @@ class Oracle:
             return Xo, {"J": Jt, "alpha": At, "margin": Mt}
         return Xo
 
-    def lockstep(self, qs, goal, xs, gs, Js, ds, alphas, amb_tol=1e-4):
-        """Replay one seed's GPU trace; returns rep [iters, 10] (see
-        orc_lockstep)."""
+    def fp32_bound(self, qs, goal, X, kc, keta):
+        """Per-element float32 error bound of the gradient at X [T, 7]
+        (orc_fp32_bound): returns (bound [T, 7], reach)."""
+        X, xp = _d(X)
+        T = X.shape[0]
+        qs, qsp = _d(qs)
+        goal, gp = _d(goal)
+        out = np.zeros((T, 7))
+        rr = lib().orc_fp32_bound(self.robot.h, self.grid.h, self._pp, qsp, gp, xp, T,
+                                  float(kc), float(keta), out.ctypes.data_as(D))
+        return out, rr
+
+    def lockstep(self, qs, goal, xs, gs, Js, ds, alphas, amb_tol=1e-4, a_coef=32.0, kc=16.0,
+                 keta=16.0):
+        """Replay one seed's GPU trace; returns rep [iters, 11] (see
+        orc_lockstep; a_coef, kc and keta are the coefficients of the
+        gradient tolerance's rounding and float32-kinematics terms)."""
         xs, xp = _d(xs)
         gs, gsp = _d(gs)
         Js, jp = _d(Js)
@@ -230,9 +247,10 @@ class Oracle:
         goal, gp = _d(goal)
         iters = alphas.shape[0]
         T = xs.shape[1]
-        rep = np.zeros((iters, 10))
+        rep = np.zeros((iters, 11))
         lib().orc_lockstep(self.robot.h, self.grid.h, self._pp, qsp, gp, T, iters, xp, gsp, jp,
-                           dp, ap, amb_tol, rep.ctypes.data_as(D))
+                           dp, ap, amb_tol, float(a_coef), float(kc), float(keta),
+                           rep.ctypes.data_as(D))
         return rep
 
     def guide(self, qs, goal, X, alpha, n):

@@ -537,6 +537,181 @@ void ambiguity(const Robot& rb, const Grid& G, const Params& P, const double* X,
   if (n_amb) *n_amb = cnt;
 }
 
+// ------------------------------------------------- float32 error bound ----
+// First-order bound, per gradient element, on how far a float32 evaluation
+// of the gradient at X can be from the exact one because its kinematics are
+// rounded: every sphere centre, joint origin and end-effector position may
+// be off by up to `delta` (metres) and every joint axis and the end-effector
+// rotation by up to `eta` (radians).  A world sample's contribution to
+// element (t, i) is f . (z_i x (c - o_i)) with the force
+// f = w_c phi'(d(c) - r) grad d(c); its change is bounded by
+//   |K| delta |z_i x (c - o_i)| + |f| (eta |c - o_i| + 2 delta),
+// K = df/dc = w_c (phi'' grad d grad d^T + phi' Hess d) (Frobenius norm),
+// where Hess d is the trilinear field's (mixed) second derivative in the
+// sample's cell and phi'' = 1/eps on the quadratic piece of the hinge.
+// The link wrenches are summed about the world origin and then projected,
+// so their rounding also scales with the moment arms about the origin:
+//   kappa_w 2^-24 (|c| + |o_i|) |f| per sample (kappa_w = the number of terms
+// a wrench component sums, bounded by the spheres per link plus one).
+// Self-collision pairs and the goal terms are bounded the same way; the
+// smoothness and limit terms use the waypoints as given and only round.
+// Row 0 (pinned) is zero.
+static void trilinear_hessian(const Grid& G, const Sample& S, double H[9]) {
+  int i = S.cell[0], j = S.cell[1], k = S.cell[2];
+  double fx = S.f[0], fy = S.f[1], fz = S.f[2];
+  double wx[2] = {1 - fx, fx}, wy[2] = {1 - fy, fy}, wz[2] = {1 - fz, fz};
+  double hxy = 0, hxz = 0, hyz = 0;
+  for (int dz = 0; dz < 2; ++dz)
+    for (int dy = 0; dy < 2; ++dy)
+      for (int dx = 0; dx < 2; ++dx) {
+        double v = node(G, i + dx, j + dy, k + dz);
+        double sx = dx ? 1.0 : -1.0, sy = dy ? 1.0 : -1.0, sz = dz ? 1.0 : -1.0;
+        hxy += sx * sy * wz[dz] * v;
+        hxz += sx * wy[dy] * sz * v;
+        hyz += wx[dx] * sy * sz * v;
+      }
+  double h2 = G.h * G.h;
+  for (int a = 0; a < 9; ++a) H[a] = 0;
+  H[1] = H[3] = hxy / h2;
+  H[2] = H[6] = hxz / h2;
+  H[5] = H[7] = hyz / h2;
+  for (int a = 0; a < 3; ++a)
+    if (S.clamped[a])
+      for (int b = 0; b < 3; ++b) H[3 * a + b] = H[3 * b + a] = 0;
+}
+
+static double norm3(const double* v) { return std::sqrt(dot3(v, v)); }
+
+// Bound of one configuration's world samples into row[0..6] with weight w.
+static void fp32_bound_world(const Robot& rb, const Grid& G, const Params& P, const double* q,
+                             double delta, double eta, double w, double* row) {
+  const double u = std::ldexp(1.0, -24);
+  int per_link[8] = {0};
+  for (int s = 0; s < rb.ns; ++s) per_link[rb.link[s]]++;
+  Frame Tf[8];
+  fk(rb, q, Tf);
+  for (int s = 0; s < rb.ns; ++s) {
+    int l = rb.link[s];
+    double c[3];
+    apply(Tf[l - 1], &rb.off[3 * s], c);
+    Sample S = sample(G, c);
+    double D = S.d - rb.rad[s];
+    double dphi = hinge_d(D, P.eps);
+    double ddphi = (D >= 0 && D < P.eps) ? 1.0 / P.eps : 0.0;
+    if (dphi == 0.0 && ddphi == 0.0) continue;
+    double Hd[9];
+    trilinear_hessian(G, S, Hd);
+    double K2 = 0;
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double k = P.wc * (ddphi * S.g[a] * S.g[b] + dphi * Hd[3 * a + b]);
+        K2 += k * k;
+      }
+    double Kn = std::sqrt(K2);
+    double fn = std::fabs(P.wc * dphi) * norm3(S.g);
+    double kw = per_link[l] + 1;
+    for (int i = 0; i < l; ++i) {
+      double zi[3] = {Tf[i].R[2], Tf[i].R[5], Tf[i].R[8]};
+      double r[3] = {c[0] - Tf[i].p[0], c[1] - Tf[i].p[1], c[2] - Tf[i].p[2]};
+      double jc[3];
+      cross(zi, r, jc);
+      double b = Kn * delta * norm3(jc) + fn * (eta * norm3(r) + 2 * delta) +
+                 kw * u * (norm3(c) + norm3(Tf[i].p)) * fn;
+      row[i] += w * b;
+    }
+  }
+}
+
+void fp32_bound(const Robot& rb, const Grid& G, const Params& P, const Problem& pr,
+                const double* X, int T, double delta, double eta, double* out) {
+  const double u = std::ldexp(1.0, -24);
+  std::fill(out, out + (size_t)T * NJ, 0.0);
+  for (int t = 1; t < T; ++t)
+    fp32_bound_world(rb, G, P, X + (size_t)t * NJ, delta, eta, 1.0, out + (size_t)t * NJ);
+  // swept sub-samples split onto the segment's two waypoints
+  for (int t = 0; t + 1 < T; ++t)
+    for (int k = 1; k <= P.nsub; ++k) {
+      double tau = (double)k / (P.nsub + 1);
+      double qi[NJ], row[NJ] = {0, 0, 0, 0, 0, 0, 0};
+      for (int j = 0; j < NJ; ++j)
+        qi[j] = (1.0 - tau) * X[(size_t)t * NJ + j] + tau * X[(size_t)(t + 1) * NJ + j];
+      fp32_bound_world(rb, G, P, qi, delta, eta, 1.0, row);
+      for (int j = 0; j < NJ; ++j) {
+        out[(size_t)t * NJ + j] += (1 - tau) * row[j];
+        out[(size_t)(t + 1) * NJ + j] += tau * row[j];
+      }
+    }
+  Frame Tf[8];
+  // self-collision pairs: the separation of two centres moves by 2 delta
+  if (P.ws != 0.0) {
+    std::vector<double> cen((size_t)rb.ns * 3);
+    for (int t = 1; t < T; ++t) {
+      fk(rb, X + (size_t)t * NJ, Tf);
+      for (int s = 0; s < rb.ns; ++s) apply(Tf[rb.link[s] - 1], &rb.off[3 * s], &cen[3 * s]);
+      for (int a = 0; a < rb.ns; ++a)
+        for (int b = 0; b < rb.ns; ++b) {
+          if (rb.link[b] - rb.link[a] < 2) continue;
+          const double* ca = &cen[3 * a];
+          const double* cb = &cen[3 * b];
+          double dv[3] = {ca[0] - cb[0], ca[1] - cb[1], ca[2] - cb[2]};
+          double dist = norm3(dv);
+          double D = dist - rb.rad[a] - rb.rad[b];
+          double dphi = hinge_d(D, P.eps);
+          double ddphi = (D >= 0 && D < P.eps) ? 1.0 / P.eps : 0.0;
+          if ((dphi == 0.0 && ddphi == 0.0) || dist == 0.0) continue;
+          double Kn = std::fabs(P.ws) * (ddphi + std::fabs(dphi) * std::sqrt(2.0) / dist);
+          double fn = std::fabs(P.ws * dphi);
+          for (int side = 0; side < 2; ++side) {
+            const double* c = side ? cb : ca;
+            int l = side ? rb.link[b] : rb.link[a];
+            for (int i = 0; i < l; ++i) {
+              double zi[3] = {Tf[i].R[2], Tf[i].R[5], Tf[i].R[8]};
+              double r[3] = {c[0] - Tf[i].p[0], c[1] - Tf[i].p[1], c[2] - Tf[i].p[2]};
+              double jc[3];
+              cross(zi, r, jc);
+              out[(size_t)t * NJ + i] += Kn * 2 * delta * norm3(jc) +
+                                         fn * (eta * norm3(r) + 2 * delta) +
+                                         8 * u * (norm3(c) + norm3(Tf[i].p)) * fn;
+            }
+          }
+        }
+    }
+  }
+  // goal pose at the last waypoint
+  {
+    fk(rb, X + (size_t)(T - 1) * NJ, Tf);
+    const Frame& E = Tf[7];
+    double e[3] = {E.p[0] - pr.pd[0], E.p[1] - pr.pd[1], E.p[2] - pr.pd[2]};
+    double M[9];
+    for (int a = 0; a < 3; ++a)
+      for (int b = 0; b < 3; ++b) {
+        double sm = 0;
+        for (int k = 0; k < 3; ++k) sm += E.R[3 * a + k] * pr.Rd[3 * b + k];
+        M[3 * a + b] = sm;
+      }
+    double wv[3] = {M[5] - M[7], M[6] - M[2], M[1] - M[3]};
+    for (int i = 0; i < NJ; ++i) {
+      double r[3] = {E.p[0] - Tf[i].p[0], E.p[1] - Tf[i].p[1], E.p[2] - Tf[i].p[2]};
+      double bp = 2 * P.wp * (eta * norm3(r) * norm3(e) + 2 * delta * norm3(e) + norm3(r) * delta);
+      double br = (P.wr / 4.0) * (eta * norm3(wv) + 4 * eta);
+      out[(size_t)(T - 1) * NJ + i] += bp + br;
+    }
+  }
+  for (int j = 0; j < NJ; ++j) out[j] = 0.0;
+}
+
+// The robot's reach: the sum of the frame translations and the largest
+// sphere offset bound the distance of every point the kinematics place
+// from the base.
+double reach(const Robot& rb) {
+  double r = 0;
+  for (int i = 0; i < 8; ++i) r += std::sqrt(rb.F[i][3] * rb.F[i][3] + rb.F[i][7] * rb.F[i][7] +
+                                             rb.F[i][11] * rb.F[i][11]);
+  double om = 0;
+  for (int s = 0; s < rb.ns; ++s) om = std::max(om, norm3(&rb.off[3 * s]));
+  return r + om;
+}
+
 // ----------------------------------------------------------- optimiser core --
 // Generic L-BFGS with the power-of-two backtracking Armijo search; the
 // objective returns J and writes the gradient.
@@ -937,6 +1112,20 @@ int orc_ambiguity(void* rb, void* g, const double* params, const double* X, int 
   return n;
 }
 
+// Float32 error bound per gradient element for X[T][7] (see fp32_bound())
+// with delta = kc 2^-24 reach and eta = keta 2^-24; returns the reach.
+double orc_fp32_bound(void* rb, void* g, const double* params, const double* qs,
+                      const double* goal, const double* X, int T, double kc, double keta,
+                      double* out) {
+  Params P = make_params(params);
+  Problem pr = make_problem(qs, goal);
+  const Robot& R = *static_cast<Robot*>(rb);
+  const double u = std::ldexp(1.0, -24);
+  double rr = reach(R);
+  fp32_bound(R, *static_cast<Grid*>(g), P, pr, X, T, kc * u * rr, keta * u, out);
+  return rr;
+}
+
 // Free-running optimisation of S seeds X0[S][T][7] for iters iterations.
 // X_out[S][T][7]; J_trace[(iters+1)][S] and alpha_trace[iters][S] nullable.
 void orc_optimize(void* rb, void* g, const double* params, const double* qs, const double* goal,
@@ -1059,10 +1248,12 @@ void orc_minimize_trace(orc_objective_cb cb, void* user, const double* params, c
 // Lockstep replay of a traced GPU run of one seed.  Inputs are the GPU's
 // per-iteration iterates x_k [iters+1][T][7], gradients g_k, costs J_k,
 // directions d_k [iters][T][7] and accepted steps alpha_k [iters].
-// Per iteration k it writes rep[k][10]:
+// Per iteration k it writes rep[k][11]:
 //   0 |J_ref(x_k) - J_k| / |J_ref|
-//   1 max_e (|g_ref - g_k| - amb_e) / G_scale   (G_scale = max(|g_ref|_inf,
-//     |abs-contributions|_inf))
+//   1 max_e (|g_ref - g_k| - amb_e - B_e - a_coef 2^-24 A_e) / |g_ref|_inf,
+//     where B_e is fp32_bound() with delta = kc 2^-24 reach and
+//     eta = keta 2^-24, and A_e the element's sum of absolute contributions
+//     (rounding of the sums)
 //   2 number of ambiguous samples at x_k
 //   3 max|d_ref - d_k| / max|d_ref|   (d_ref from the replayed history and g_k)
 //   4 alpha_ref (FP64 line search along the GPU's d_k from x_k)
@@ -1070,10 +1261,13 @@ void orc_minimize_trace(orc_objective_cb cb, void* user, const double* params, c
 //   6 max|x_{k+1} - (x_k + alpha_k d_k)|
 //   7 1 if the GPU's history clear/push decision differs from the replay
 //   8 gtd_ref (g_k . d_k in FP64)
-//   9 G_scale
+//   9 |g_ref|_inf
+//  10 max_e (|g_ref - g_k| - amb_e - B_e - 1e-4 |g_ref|_inf) / (2^-24 A_e):
+//     the rounding coefficient the element needs beyond the other terms
 void orc_lockstep(void* rbp, void* gp, const double* params, const double* qs, const double* goal,
                   int T, int iters, const double* xs, const double* gs, const double* Js,
-                  const double* ds, const double* alphas, double amb_tol, double* rep) {
+                  const double* ds, const double* alphas, double amb_tol, double a_coef,
+                  double kc, double keta, double* rep) {
   Params P = make_params(params);
   Problem pr = make_problem(qs, goal);
   const Robot& R = *static_cast<Robot*>(rbp);
@@ -1082,23 +1276,31 @@ void orc_lockstep(void* rbp, void* gp, const double* params, const double* qs, c
   int n = (T - 1) * NJ;
   TrajObjective obj{&R, &G, &P, &pr, T, {}, {}};
   History H;
-  std::vector<double> gref(stride), A(stride), amb(stride), d(n), xt(n);
+  std::vector<double> gref(stride), A(stride), amb(stride), fb(stride), d(n), xt(n);
+  const double u = std::ldexp(1.0, -24);
+  const double delta = kc * u * reach(R), eta = keta * u;
   for (int k = 0; k < iters; ++k) {
     const double* xk = xs + k * stride;
     const double* gk = gs + k * stride;
     const double* dk = ds + k * stride;
-    double* r = rep + (size_t)k * 10;
+    double* r = rep + (size_t)k * 11;
     double Jref = cost(R, G, P, pr, xk, T, gref.data(), A.data(), nullptr);
     int na = 0;
     ambiguity(R, G, P, xk, T, amb_tol, amb.data(), &na);
-    double gscale = std::max(norm_inf(gref.data(), (int)stride), norm_inf(A.data(), (int)stride));
-    double gerr = 0;
-    for (size_t e = NJ; e < stride; ++e)
-      gerr = std::max(gerr, (std::fabs(gref[e] - gk[e]) - amb[e]) / gscale);
+    fp32_bound(R, G, P, pr, xk, T, delta, eta, fb.data());
+    double gn = norm_inf(gref.data(), (int)stride);
+    double gerr = -std::numeric_limits<double>::infinity(), cneed = 0;
+    for (size_t e = NJ; e < stride; ++e) {
+      double ex = std::fabs(gref[e] - gk[e]) - amb[e] - fb[e];
+      gerr = std::max(gerr, (ex - a_coef * u * A[e]) / std::max(gn, 1e-300));
+      double over = ex - 1e-4 * gn;
+      if (over > 0) cneed = std::max(cneed, over / std::max(u * A[e], 1e-300));
+    }
     r[0] = std::fabs(Jref - Js[k]) / std::fabs(Jref);
     r[1] = gerr;
     r[2] = na;
-    r[9] = gscale;
+    r[9] = gn;
+    r[10] = cneed;
     // direction from the replayed history and the GPU's gradient
     size_t before = H.pairs.size();
     bool cleared = direction(P, H, gk + NJ, n, d.data());

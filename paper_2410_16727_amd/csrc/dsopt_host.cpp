@@ -344,7 +344,8 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   if (!std::isfinite(prm->w_self) || prm->swept_samples < 0 || prm->swept_samples > 8 ||
       !(prm->eps > 0) || prm->history < 1 || prm->history > DS_MAX_HISTORY || prm->n_ls < 1 ||
       prm->n_ls > DS_MAX_LS || prm->n_iters < 0 || prm->block_iters < 1 || !(prm->dt > 0) ||
-      !(prm->delta0 > 0) || !(prm->step_max > 0) ||
+      !(prm->delta0 > 0) || !(prm->step_max > 0) || !(prm->v_limit > 0) ||
+      !(prm->a_limit > 0) || !(prm->j_limit > 0) ||
       !(prm->waves_per_seed == 1 || prm->waves_per_seed == 2 || prm->waves_per_seed == 4 ||
         prm->waves_per_seed == 8))
     return fail(DS_ERR_INVALID, "invalid parameters");
@@ -397,6 +398,7 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   P.far = prm->eps + 1e-5f;
   P.skip = prm->exact_gathers ? 0 : 1;
   P.drain = prm->serve_drain ? 1 : 0;
+  P.vlim = prm->v_limit; P.alim = prm->a_limit; P.jlim = prm->j_limit;
   p->blocks_per_cu = optimize_blocks_per_cu(P.waves, params_ext(P));
 
   p->robot_off = p->arena.alloc(sizeof(RobotDev));
@@ -441,9 +443,15 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
   size_t cells = (size_t)(nx - 1) * (ny - 1) * (nz - 1);
   size_t rec_bytes = cells * 32;
   if (rec_bytes > 0x7fffffffull) return fail(DS_ERR_INVALID, "grid too large (> 2^26 cells)");
+  // the kernels form a cell's record index as ix + (nx-1) * ((ny-1) * iz + iy)
+  // with 24-bit multiplies: both factors of each product must stay below 2^24
+  if ((size_t)(ny - 1) * (nz - 1) >= (1u << 24) || (size_t)(nx - 1) >= (1u << 24))
+    return fail(DS_ERR_INVALID, "grid too flat: (ny-1)*(nz-1) must be < 2^24");
   hipStream_t s = static_cast<hipStream_t>(stream);
   poll_deferred(p, false);
   if (p->scenes.count(scene_id)) {
+    if (ds_serve_uses_scene(p, scene_id))
+      return fail(DS_ERR_BUSY, "scene %d is used by a serving request", scene_id);
     HIP_TRY(hipDeviceSynchronize());
     p->arena.release(p->scenes[scene_id].off);
     p->scenes.erase(scene_id);
@@ -459,7 +467,7 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
     if ((long long)cdx * cdy * cdz <= COARSE_MAX) break;
   }
   const size_t coarse_at = (rec_bytes + 255) / 256 * 256;
-  size_t off = arena_alloc(p, coarse_at + COARSE_MAX * sizeof(float));
+  size_t off = arena_alloc(p, coarse_at + COARSE_MAX * sizeof(uint16_t));
   if (off == SIZE_MAX) return fail(DS_ERR_NOMEM, "arena full (scene %d, %zu B)", scene_id, rec_bytes);
   const float* src = vals;
   size_t tmp_off = SIZE_MAX;
@@ -479,7 +487,7 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
     src = reinterpret_cast<const float*>(p->arena.ptr(tmp_off));
   }
   HIP_TRY(launch_esdf_pack(src, nx, ny, nz, reinterpret_cast<float4*>(p->arena.ptr(off)), s));
-  float* coarse = reinterpret_cast<float*>(p->arena.ptr(off) + coarse_at);
+  uint16_t* coarse = reinterpret_cast<uint16_t*>(p->arena.ptr(off) + coarse_at);
   HIP_TRY(launch_coarse(src, nx, ny, nz, cshift, cdx, cdy, cdz, coarse, s));
   if (tmp_off != SIZE_MAX)
     if (int rc = defer_free(p, tmp_off, s)) return rc;
@@ -542,6 +550,8 @@ int ds_esdf_release(ds_plan* p, int32_t scene_id) {
   if (!p) return fail(DS_ERR_INVALID, "NULL plan");
   auto it = p->scenes.find(scene_id);
   if (it == p->scenes.end()) return fail(DS_ERR_NOT_FOUND, "scene %d is not resident", scene_id);
+  if (ds_serve_uses_scene(p, scene_id))
+    return fail(DS_ERR_BUSY, "scene %d is used by a serving request", scene_id);
   HIP_TRY(hipDeviceSynchronize());
   p->arena.release(it->second.off);
   p->scenes.erase(it);
@@ -683,5 +693,4 @@ int ds_sphere_centres(ds_plan* p, const float* X, int S, int T, float* out, void
 
 }  // extern "C"
 
-// Serving lives in dsopt_serve.cpp; until it is linked these stubs keep the
-// ABI complete.
+

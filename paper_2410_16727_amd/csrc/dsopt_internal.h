@@ -35,21 +35,24 @@ struct ParamsDev {
   float far;             // a block minimum >= radius + far proves a zero hinge
   int32_t skip;          // use the coarse table (0: gather every sample)
   int32_t drain;         // serving: run to completion when nobody waits
+  float vlim, alim, jlim;   // velocity / acceleration / jerk limits (motion time)
 };
 
 // One resident scene: the 8 corners of cell (i,j,k) are the 32-byte record
 // i + (nx-1)*(j + (ny-1)*k): [c000 c100 c010 c110 | c001 c101 c011 c111].
 // Coarse table: the minimum node distance over each block of 2^cshift
 // cells per axis (node range of the block's cells, inclusive), at most
-// COARSE_MAX blocks, x fastest.
+// COARSE_MAX blocks, x fastest, as IEEE half-precision values rounded
+// towards minus infinity (a lower bound of the float minimum: 8 KB).
 constexpr int COARSE_MAX = 4096;
+constexpr int COARSE_FLOATS = COARSE_MAX / 2;   // the table's size in 4-byte words
 
 struct SceneDev {
   const float4* rec;
   int32_t nx, ny, nz;    // node counts
   float ox, oy, oz, inv_h;
   uint32_t bytes;        // size of the record array
-  const float* coarse;   // [cdz][cdy][cdx] block minima
+  const uint16_t* coarse;   // [cdz][cdy][cdx] block minima (half bits, rounded down)
   int32_t cshift, cdx, cdy, cdz;
 };
 
@@ -109,6 +112,8 @@ struct SlotDev {
 
 // Releases the serving state of a plan (dsopt_serve.cpp).
 void ds_serve_free(ds_plan* plan);
+// True while a queued or admitted serving request uses the scene.
+bool ds_serve_uses_scene(const ds_plan* plan, int32_t scene_id);
 
 // Launch wrappers (dsopt_kernels.hip).  `ext` selects the kernel variants
 // with the optional terms (self-collision, swept sub-samples) compiled in.
@@ -117,7 +122,7 @@ inline bool params_ext(const ParamsDev& P) { return P.ws != 0.f || P.nsub > 0; }
 hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* rec,
                             hipStream_t s);
 hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
-                         int cdz, float* out, hipStream_t s);
+                         int cdz, uint16_t* out, hipStream_t s);
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
                            int max_iters, int waves, bool ext, hipStream_t s);

@@ -135,8 +135,9 @@ __device__ __forceinline__ Goal make_goal(const ProbDev& pb) {
 struct Sampler {
   __amdgpu_buffer_rsrc_t rsrc;
   float ox, oy, oz, inv_h, nxm1, nym1, nzm1;
+  float fxm2, fym2, fzm2;          // last cell index per axis, as floats
   int nxm2, nym2, nzm2, cx, cy;    // cells along x and y
-  const DS_LDS float* cm;          // the scene's coarse table, staged in LDS
+  const DS_LDS uint16_t* cm;       // the scene's coarse table (half bits), staged in LDS
   int cshift, cdx, cdy;
 };
 
@@ -146,6 +147,7 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
   s.ox = sc.ox; s.oy = sc.oy; s.oz = sc.oz; s.inv_h = sc.inv_h;
   s.nxm1 = (float)(sc.nx - 1); s.nym1 = (float)(sc.ny - 1); s.nzm1 = (float)(sc.nz - 1);
   s.nxm2 = sc.nx - 2; s.nym2 = sc.ny - 2; s.nzm2 = sc.nz - 2;
+  s.fxm2 = (float)s.nxm2; s.fym2 = (float)s.nym2; s.fzm2 = (float)s.nzm2;
   s.cx = sc.nx - 1;
   s.cy = sc.ny - 1;
   s.cm = nullptr;
@@ -156,12 +158,19 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
 }
 
 // Copy the scene's coarse table into LDS (threads tid = 0..nth-1 of the
-// group that shares it; the caller synchronises them afterwards).
-__device__ __forceinline__ void stage_coarse(const SceneDev& sc, DS_LDS float* dst, int tid,
+// group that shares it; the caller synchronises them afterwards), two
+// entries per 4-byte word.
+__device__ __forceinline__ void stage_coarse(const SceneDev& sc, DS_LDS uint16_t* dst, int tid,
                                              int nth) {
-  const int n = sc.cdx * sc.cdy * sc.cdz;
-  const DS_GLOBAL float* src = glb(sc.coarse);
-  for (int i = tid; i < n; i += nth) dst[i] = src[i];
+  const int n = (sc.cdx * sc.cdy * sc.cdz + 1) / 2;
+  const DS_GLOBAL uint32_t* src = glb(reinterpret_cast<const uint32_t*>(sc.coarse));
+  DS_LDS uint32_t* d32 = (DS_LDS uint32_t*)dst;
+  for (int i = tid; i < n; i += nth) d32[i] = src[i];
+}
+
+// A coarse-table entry as a float.
+__device__ __forceinline__ float coarse_at(const Sampler& S, int idx) {
+  return (float)__builtin_bit_cast(_Float16, S.cm[idx]);
 }
 
 // Cell lookup for a query point: clamp u = (p - origin) / voxel into the
@@ -202,12 +211,25 @@ __device__ __forceinline__ Cell locate(const Sampler& S, float px, float py, flo
   return c;
 }
 
+// The coarse block of the cell locate() picks for a query point, alone:
+// for u >= 0, min(trunc(min(u, n-1)), n-2) == trunc(min(u, n-2)), so the
+// block index is the same with a third of the arithmetic.
+__device__ __forceinline__ int block_of(const Sampler& S, float px, float py, float pz) {
+  const int ix = (int)fminf(fmaxf((px - S.ox) * S.inv_h, 0.f), S.fxm2);
+  const int iy = (int)fminf(fmaxf((py - S.oy) * S.inv_h, 0.f), S.fym2);
+  const int iz = (int)fminf(fmaxf((pz - S.oz) * S.inv_h, 0.f), S.fzm2);
+  const unsigned crow =
+      __umul24((unsigned)S.cdy, (unsigned)(iz >> S.cshift)) + (unsigned)(iy >> S.cshift);
+  return (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
+}
+
 // True when the coarse table proves the sample's hinge is zero: every
 // corner of every cell in the block is at least radius + eps (+ margin)
 // from the nearest obstacle, and a trilinear blend stays within its corner
 // range.
-__device__ __forceinline__ bool far_sample(const Sampler& S, const Cell& c, float r, float far) {
-  return S.cm[c.cidx] >= r + far;
+__device__ __forceinline__ bool far_point(const Sampler& S, float px, float py, float pz, float r,
+                                          float far) {
+  return coarse_at(S, block_of(S, px, py, pz)) >= r + far;
 }
 
 // Trilinear blend of a cell record (a: z0 corners, b: z1 corners) and, with
@@ -525,14 +547,17 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
         pr_[l] = sp.w;
         // the coarse minimum is read here and tested after the chain, so
         // no link waits for its lookup before the next frame
-        if (SKIP) pcm_[l] = S.cm[locate(S, pc_[l][0], pc_[l][1], pc_[l][2]).cidx];
+        if (SKIP) pcm_[l] = coarse_at(S, block_of(S, pc_[l][0], pc_[l][1], pc_[l][2]));
       }
       continue;
     }
     float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool link_used = false;
     // chunks of CH spheres per lane (this lane takes every (W*L)-th sphere
-    // of the link): issue every record load of the chunk, then consume them
-    // in sphere order -- CH gathers in flight per lane
+    // of the link): test each sample against the coarse table, locate its
+    // cell and issue its record loads only when the test cannot prove a
+    // zero hinge, then consume the chunk in sphere order -- CH gathers in
+    // flight per lane
     for (int s = s0; s < s1; s += LW * CH) {
       Cell cl[CH];
       float4 ra[CH], rz[CH];
@@ -548,15 +573,16 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
           cys[k] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
           czs[k] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
           rr[k] = sp.w;
-          cl[k] = locate(S, cxs[k], cys[k], czs[k]);
-          if (SKIP && far_sample(S, cl[k], sp.w, P.far)) {
+          if (SKIP && far_point(S, cxs[k], cys[k], czs[k], sp.w, P.far)) {
             use[k] = false;   // zero hinge, zero gradient
           } else {
+            cl[k] = locate(S, cxs[k], cys[k], czs[k]);
             ra[k] = load_rec(S, cl[k].off);
             rz[k] = load_rec(S, cl[k].off + 16);
             ++ng;
           }
         }
+        link_used |= use[k];
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
@@ -565,7 +591,9 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
                             clr, FM);
       }
     }
-    if (GRAD) project(tw, l, FM, g);
+    // a link none of whose samples reached the hinge in this wavefront has
+    // a zero wrench everywhere: its projection would add zeros
+    if (GRAD && __any(link_used)) project(tw, l, FM, g);
   }
   if (PIPE) {
     // issue the record loads of the samples that can reach the hinge
@@ -1178,14 +1206,20 @@ __device__ __forceinline__ int finalize(const TileCtx& c, const float* x, Team& 
 #pragma unroll
   for (int j = 0; j < NJ; ++j) inlim &= (x[j] >= c.rb->qlo[j] && x[j] <= c.rb->qhi[j]) ? 1 : 0;
   float okf = grp_min((c.active && !inlim) ? 0.f : 1.f, c.G);
-  // interior third differences
-  float jm = 0.f;
+  // trajectory metrics: largest first, second and third differences
+  float vm = 0.f, am = 0.f, jm = 0.f;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
     float q1 = __shfl_down(x[j], 1), q2 = __shfl_down(x[j], 2), q3 = __shfl_down(x[j], 3);
-    float v = q3 - 3.f * q2 + 3.f * q1 - x[j];
-    jm = fmaxf(jm, (c.t + 3 < c.T) ? fabsf(v) : 0.f);
+    float v1 = q1 - x[j];
+    float v2 = q2 - 2.f * q1 + x[j];
+    float v3 = q3 - 3.f * q2 + 3.f * q1 - x[j];
+    vm = fmaxf(vm, (c.t + 1 < c.T) ? fabsf(v1) : 0.f);
+    am = fmaxf(am, (c.t + 2 < c.T) ? fabsf(v2) : 0.f);
+    jm = fmaxf(jm, (c.t + 3 < c.T) ? fabsf(v3) : 0.f);
   }
+  vm = grp_max(vm, c.G);
+  am = grp_max(am, c.G);
   jm = grp_max(jm, c.G);
   if (c.owner && c.t < c.T) {
     DS_GLOBAL float* ft = glb(c.pb->final_traj) + ((size_t)c.seed * c.T + c.t) * NJ;
@@ -1203,8 +1237,16 @@ __device__ __forceinline__ int finalize(const TileCtx& c, const float* x, Team& 
     sr.clearance = clr;
     sr.pos_err = perr;
     sr.rot_err = rerr;
-    float dt3 = c.P.dt * c.P.dt * c.P.dt;
-    sr.max_jerk = jm / dt3;
+    const float dt = c.P.dt;
+    sr.max_jerk = jm / (dt * dt * dt);
+    sr.max_vel = vm / dt;
+    sr.max_acc = am / (dt * dt);
+    sr.within_vel = sr.max_vel <= c.P.vlim ? 1 : 0;
+    // the uniform slow-down s >= 1 that meets the velocity, acceleration and
+    // jerk limits (they scale as 1/s, 1/s^2, 1/s^3)
+    const float sc = fmaxf(fmaxf(1.f, sr.max_vel / c.P.vlim),
+                           fmaxf(sqrtf(sr.max_acc / c.P.alim), cbrtf(sr.max_jerk / c.P.jlim)));
+    sr.motion_time = sc * (float)(c.T - 1) * dt;
     sr.valid = isfinite(Jr) ? 1 : 0;
     sr.collision_free = clr > 0.f ? 1 : 0;
     sr.within_limits = okf > 0.5f ? 1 : 0;
@@ -1219,6 +1261,8 @@ __device__ __forceinline__ int finalize(const TileCtx& c, const float* x, Team& 
     o->collision_free = sr.collision_free; o->within_limits = sr.within_limits;
     o->success = sr.success; o->valid = sr.valid; o->n_evals_cost = sr.n_evals_cost;
     o->n_evals_grad = sr.n_evals_grad;
+    o->max_vel = sr.max_vel; o->max_acc = sr.max_acc; o->motion_time = sr.motion_time;
+    o->within_vel = sr.within_vel;
   }
   return r.ng;
 }
@@ -1236,7 +1280,7 @@ enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
 template <bool LDS_HIST, bool EXT>
 __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
                          const ProbDev* __restrict__ probs, const TileDev& td, int max_iters,
-                         Team& tm, float* hist_lds, float* coarse_lds, float* dir_lds) {
+                         Team& tm, float* hist_lds, uint16_t* coarse_lds, float* dir_lds) {
   TileCtx c;
   c.rb = rb;
   c.P = *pp;
@@ -1457,8 +1501,11 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
 // all of them reach every barrier.  Variants: TEAM (W > 1, history ring
 // in LDS) and EXT (self-collision and swept terms compiled in); the plain
 // variant carries no code for the optional terms.
+#ifndef DSOPT_WPE
+#define DSOPT_WPE 2
+#endif
 template <bool TEAM, bool EXT>
-__global__ void __launch_bounds__(MAX_TEAM * WAVE)
+__global__ void __launch_bounds__(TEAM ? MAX_TEAM * WAVE : BLOCK, TEAM ? 1 : DSOPT_WPE)
 k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
            const ProbDev* __restrict__ probs, const TileDev* __restrict__ tiles,
            const int* __restrict__ tile_list, const int* __restrict__ n_tiles_dev, int n_tiles,
@@ -1494,12 +1541,13 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
     TileDev td = tiles[ti];
     if constexpr (TEAM) {
       run_tile<true, EXT>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE,
-                          s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS,
-                          s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS + COARSE_MAX);
+                          reinterpret_cast<uint16_t*>(s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS),
+                          s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS + COARSE_FLOATS);
       __syncthreads();   // the LDS ring is free for the next tile
     } else {
       run_tile<false, EXT>(rb, pp, probs, td, max_iters, tm, nullptr,
-                           s_dyn + (threadIdx.x / WAVE) * COARSE_MAX, nullptr);
+                           reinterpret_cast<uint16_t*>(s_dyn + (threadIdx.x / WAVE) * COARSE_FLOATS),
+                           nullptr);
     }
   }
 }
@@ -1551,10 +1599,13 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
       out.cost = r.cost;
       out.min_clearance_m = r.clearance;
       out.max_jerk = r.max_jerk;
+      out.max_vel = r.max_vel;
+      out.motion_time = r.motion_time;
     } else {
       out.success = 0;
       out.collision_free = 0;
       out.pos_err_m = out.rot_err_rad = out.cost = out.min_clearance_m = out.max_jerk = NAN;
+      out.max_vel = out.motion_time = NAN;
     }
     *pb.result = out;
     if (pb.landing) *reinterpret_cast<ds_result*>(pb.landing) = out;
@@ -1601,7 +1652,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
        int with_grad, int W) {
   extern __shared__ float s_team[];
-  __shared__ float s_cm[COARSE_MAX];
+  __shared__ uint16_t s_cm[COARSE_MAX];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
@@ -1642,7 +1693,7 @@ k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
         int n_steps, float* __restrict__ J_out, int W) {
   extern __shared__ float s_team[];
-  __shared__ float s_cm[COARSE_MAX];
+  __shared__ uint16_t s_cm[COARSE_MAX];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
@@ -1737,7 +1788,7 @@ constexpr int COARSE_THREADS = 256;
 
 __global__ void __launch_bounds__(COARSE_THREADS)
 k_coarse(const float* __restrict__ v, int nx, int ny, int nz, int shift, int cdx, int cdy,
-         float* __restrict__ out) {
+         uint16_t* __restrict__ out) {
   __shared__ float s_min[COARSE_THREADS / WAVE];
   const int b = blockIdx.x;
   const int bx = b % cdx, by = (b / cdx) % cdy, bz = b / (cdx * cdy);
@@ -1757,7 +1808,17 @@ k_coarse(const float* __restrict__ v, int nx, int ny, int nz, int shift, int cdx
   if (threadIdx.x == 0) {
     float r = s_min[0];
     for (int w = 1; w < COARSE_THREADS / WAVE; ++w) r = fminf(r, s_min[w]);
-    out[b] = r;
+    // half precision rounded towards minus infinity: the nearest half,
+    // stepped down one unit when it lies above r (overflow to +inf steps
+    // to the largest finite half; NaN stays NaN and never proves a skip)
+    _Float16 hv = (_Float16)r;
+    uint16_t bits = __builtin_bit_cast(uint16_t, hv);
+    if ((float)hv > r) {
+      if (bits == 0x0000u) bits = 0x8001u;
+      else if (bits & 0x8000u) bits = (uint16_t)(bits + 1u);
+      else bits = (uint16_t)(bits - 1u);
+    }
+    out[b] = bits;
   }
 }
 
@@ -1841,7 +1902,7 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
 }
 
 hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
-                         int cdz, float* out, hipStream_t s) {
+                         int cdz, uint16_t* out, hipStream_t s) {
   (void)cdz;
   hipLaunchKernelGGL(k_coarse, dim3(cdx * cdy * cdz), dim3(COARSE_THREADS), 0, s, vals, nx, ny,
                      nz, shift, cdx, cdy, out);
@@ -1853,9 +1914,9 @@ int team_block(int W) { return (W > 1 ? W : WAVES_PER_BLOCK) * WAVE; }
 // buffered), history ring, coarse table and direction broadcast; single
 // wavefronts: one coarse table each
 size_t team_lds(int W) {
-  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS + COARSE_MAX + DL_FLOATS) *
+  return W > 1 ? ((size_t)2 * W * PART * WAVE + H_FLOATS + COARSE_FLOATS + DL_FLOATS) *
                      sizeof(float)
-               : (size_t)WAVES_PER_BLOCK * COARSE_MAX * sizeof(float);
+               : (size_t)WAVES_PER_BLOCK * COARSE_FLOATS * sizeof(float);
 }
 
 using OptKernel = void (*)(const RobotDev*, const ParamsDev*, const ProbDev*, const TileDev*,

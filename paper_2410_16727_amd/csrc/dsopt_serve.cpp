@@ -132,6 +132,21 @@ void ds_serve_free(ds_plan* p) {
   p->serve = nullptr;
 }
 
+bool ds_serve_uses_scene(const ds_plan* p, int32_t scene_id) {
+  if (!p || !p->serve) return false;
+  const Serve* sv = p->serve;
+  for (uint64_t t : sv->queue) {
+    auto it = sv->reqs.find(t);
+    if (it != sv->reqs.end() && it->second.prob.scene_id == scene_id) return true;
+  }
+  for (const Slot& sl : sv->slots) {
+    if (!sl.ticket) continue;
+    auto it = sv->reqs.find(sl.ticket);
+    if (it != sv->reqs.end() && it->second.prob.scene_id == scene_id) return true;
+  }
+  return false;
+}
+
 namespace {
 
 // Take the results of completed replays (in order).  With `block`, wait

@@ -61,7 +61,8 @@ class Params(C.Structure):
                 ("tol_rot", C.c_float), ("n_iters", C.c_int32), ("block_iters", C.c_int32),
                 ("waves_per_seed", C.c_int32), ("w_self", C.c_float),
                 ("swept_samples", C.c_int32), ("exact_gathers", C.c_int32),
-                ("serve_drain", C.c_int32)]
+                ("serve_drain", C.c_int32), ("v_limit", C.c_float), ("a_limit", C.c_float),
+                ("j_limit", C.c_float)]
 
 
 class Problem(C.Structure):
@@ -74,14 +75,17 @@ class Result(C.Structure):
     _fields_ = [("best_seed", C.c_int32), ("success", C.c_int32), ("collision_free", C.c_int32),
                 ("n_valid_seeds", C.c_int32), ("pos_err_m", C.c_float),
                 ("rot_err_rad", C.c_float), ("cost", C.c_float), ("min_clearance_m", C.c_float),
-                ("max_jerk", C.c_float), ("n_iters", C.c_int32)]
+                ("max_jerk", C.c_float), ("n_iters", C.c_int32), ("max_vel", C.c_float),
+                ("motion_time", C.c_float)]
 
 
 class SeedResult(C.Structure):
     _fields_ = [("cost", C.c_float), ("clearance", C.c_float), ("pos_err", C.c_float),
                 ("rot_err", C.c_float), ("max_jerk", C.c_float), ("collision_free", C.c_int32),
                 ("within_limits", C.c_int32), ("success", C.c_int32), ("valid", C.c_int32),
-                ("n_evals_cost", C.c_int32), ("n_evals_grad", C.c_int32), ("n_gathers", C.c_uint32)]
+                ("n_evals_cost", C.c_int32), ("n_evals_grad", C.c_int32), ("n_gathers", C.c_uint32),
+                ("max_vel", C.c_float), ("max_acc", C.c_float), ("motion_time", C.c_float),
+                ("within_vel", C.c_int32)]
 
 
 class LatencyStats(C.Structure):
@@ -187,6 +191,9 @@ def params_struct(p: dict, n_iters: int, block_iters: int = 10):
     s.swept_samples = int(p.get("swept_samples", 0))
     s.exact_gathers = int(p.get("exact_gathers", 0))
     s.serve_drain = int(p.get("serve_drain", 0))
+    s.v_limit = float(p.get("v_limit", 2.5))
+    s.a_limit = float(p.get("a_limit", 10.0))
+    s.j_limit = float(p.get("j_limit", 5000.0))
     return s
 
 

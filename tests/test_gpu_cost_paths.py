@@ -15,7 +15,7 @@ import oracle  # noqa: E402
 from paper_2410_16727_amd import dsopt  # noqa: E402
 from workloads import configs, gen, params  # noqa: E402
 
-from test_gpu_parity import check_cost_grad, random_trajs, setup  # noqa: E402
+from test_gpu_parity import check_cost_grad, guidance_lockstep, random_trajs, setup  # noqa: E402
 
 
 @pytest.mark.parametrize("S,T", [(2100, 16), (3, 40)])
@@ -34,18 +34,8 @@ def test_guidance_single_wavefronts():
     plan.upload_scene(0, scene.grid, scene.voxel, scene.origin)
     X = gen.random_trajectories(np.random.default_rng(81), 2100, 16, prob.q_start)
     print("guidance, 2100 seeds", flush=True)
-    Xd = torch.from_numpy(X).cuda()
-    alpha, n = 2e-5, 3
-    J = plan.guide(0, prob.q_start, prob.goal, Xd, alpha, n).cpu().numpy()
     O = oracle.Oracle(robot, scene, params.as_list(), threads=8)
-    ref = O.guide(prob.q_start, prob.goal, X.astype(np.float64), alpha, n)
-    Xg = Xd.cpu().numpy().astype(np.float64)
-    g0 = O.cost(prob.q_start, prob.goal, X.astype(np.float64), grad=True, absg=True)
-    scale = max(np.abs(g0["G"]).max(), np.abs(g0["A"]).max())
-    err = np.abs(Xg - ref)
-    tol = n * alpha * 1e-3 * scale + 1e-6
-    assert np.quantile(err, 0.99) <= tol
-    assert err.max() <= 100 * tol
-    Jref = O.cost(prob.q_start, prob.goal, Xg)["J"]
+    J, Xg = guidance_lockstep(plan, O, prob, X, 2e-5, 3)
+    Jref = O.cost(prob.q_start, prob.goal, Xg.astype(np.float64))["J"]
     assert (np.abs(J - Jref) / Jref).max() < 1e-4
     plan.close()

@@ -36,9 +36,35 @@ def test_library_exports_every_declared_symbol():
     assert isinstance(L.ds_last_error(), bytes)
 
 
-def test_struct_sizes_match_header_layout():
+STRUCTS = {"ds_sphere": "Sphere", "ds_robot": "Robot", "ds_params": "Params",
+           "ds_problem": "Problem", "ds_result": "Result", "ds_seed_result": "SeedResult",
+           "ds_latency_stats": "LatencyStats"}
+
+
+def test_struct_layouts_match_header(tmp_path):
+    """Every ctypes record of the binding has the size and field offsets the
+    C compiler gives the header's struct (compiled here with gcc)."""
+    import subprocess
     from paper_2410_16727_amd import dsopt
-    assert ctypes.sizeof(dsopt.Sphere) == 20
-    assert ctypes.sizeof(dsopt.Result) == 40
-    assert ctypes.sizeof(dsopt.SeedResult) == 48
-    assert ctypes.sizeof(dsopt.Problem) == 16 + 56 + 16
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "dsopt.h"', 'int main(void) {']
+    for cname, pyname in STRUCTS.items():
+        lines.append(f'  printf("{cname} size %zu\\n", sizeof({cname}));')
+        for field, _ in getattr(dsopt, pyname)._fields_:
+            lines.append(f'  printf("{cname} {field} %zu\\n", offsetof({cname}, {field}));')
+    lines += ["  return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.check_call(["gcc", "-std=c99", "-I", os.path.join(ROOT, "include"), str(src), "-o",
+                           str(exe)])
+    out = subprocess.check_output([str(exe)], text=True).split("\n")
+    got = {}
+    for line in out:
+        if line:
+            c, f, v = line.split()
+            got[(c, f)] = int(v)
+    for cname, pyname in STRUCTS.items():
+        cls = getattr(dsopt, pyname)
+        assert ctypes.sizeof(cls) == got[(cname, "size")], cname
+        for field, _ in cls._fields_:
+            assert getattr(cls, field).offset == got[(cname, field)], (cname, field)

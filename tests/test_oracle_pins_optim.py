@@ -331,3 +331,69 @@ def test_ambiguity_bound_zero_away_from_faces(oracle_lib):
         assert np.min(np.abs(u - np.round(u))) > 0.05
         amb, n = O.ambiguity(_X(q1))
         assert n == 0 and np.all(amb == 0)
+
+
+# ------------------------------------------------------- float32 bound ----
+
+def _frame_motion(O, X, Y):
+    """Largest displacement of any sphere centre, joint origin or the end
+    effector, and largest rotation angle of any link frame, between the
+    configurations of X and Y (row by row)."""
+    dmax = amax = 0.0
+    for t in range(X.shape[0]):
+        R0, p0 = O.fk(X[t])
+        R1, p1 = O.fk(Y[t])
+        dmax = max(dmax, np.linalg.norm(p1 - p0, axis=1).max())
+        for i in range(8):
+            c = (np.trace(R0[i].T @ R1[i]) - 1.0) / 2.0
+            amax = max(amax, math.acos(min(1.0, max(-1.0, c))))
+    c0, c1 = O.spheres(X), O.spheres(Y)
+    dmax = max(dmax, np.linalg.norm(c1 - c0, axis=-1).max())
+    return dmax, amax
+
+
+@pytest.mark.parametrize("key", ["B", "A"])
+def test_fp32_bound_covers_kinematic_perturbations(key):
+    """The float32 bound B_e is a first-order bound of how far the gradient
+    moves when every centre, origin and the end effector move by at most
+    delta and every frame turns by at most eta.  Moving the configuration
+    by a tiny random dq does exactly that (delta, eta measured from the
+    kinematics): the exact change of every gradient element must stay below
+    B_e (plus the cell-face ambiguity for the few samples that cross a cell
+    face), with the smoothness and limit terms off (they depend on the
+    waypoints only).  The bound must also not be vacuous: below 200 x the
+    largest change seen.  Catches: a dropped hinge-curvature or
+    field-curvature term, a missing moment arm, or a bound that ignores the
+    goal terms."""
+    robot = configs.robot(key)
+    sc = configs.scenes(key, only={0})[0]
+    prob = configs.problems(key)[0]
+    pl = params.as_list({"lambda_v": 0, "lambda_a": 0, "lambda_j": 0, "w_limit": 0})
+    O = oracle.Oracle(robot, sc, pl, threads=4)
+    X = configs.seeds_for(key, 0, prob, S=4).astype(np.float64)
+    u = 2.0 ** -24
+    rng = np.random.default_rng(90)
+    worst_ratio, biggest = 0.0, 0.0
+    for s in range(X.shape[0]):
+        g0 = O.cost(prob.q_start, prob.goal, X[s], grad=True)["G"][0]
+        for trial in range(3):
+            Y = X[s].copy()
+            Y[1:] += rng.uniform(-1, 1, Y[1:].shape) * 1e-5
+            delta, eta = _frame_motion(O, X[s], Y)
+            fb, reach = O.fp32_bound(prob.q_start, prob.goal, X[s], delta / (u * 1.0), eta / u)
+            # the bound scales delta by the reach: undo it
+            fb, _ = O.fp32_bound(prob.q_start, prob.goal, X[s], delta / (u * reach), eta / u)
+            g1 = O.cost(prob.q_start, prob.goal, Y, grad=True)["G"][0]
+            amb, _ = O.ambiguity(X[s], tol=5e-3)
+            diff = np.abs(g1 - g0)
+            assert np.all(diff <= 1.05 * fb + amb + 1e-9), (s, float((diff - fb - amb).max()))
+            act = diff[amb == 0]
+            bnd = fb[amb == 0]
+            big = act > 1e-3 * act.max()
+            if big.any():
+                worst_ratio = max(worst_ratio, float((act[big] / bnd[big]).max()))
+            biggest = max(biggest, float(act.max()))
+    assert worst_ratio <= 1.05
+    # not vacuous: some element's bound is within 200x of its actual change
+    assert worst_ratio > 1.0 / 200.0, worst_ratio
+    assert biggest > 0
