@@ -294,6 +294,31 @@ int ds_sphere_centres(ds_plan* plan, const float* X, int S, int T, float* out, v
 int ds_kernel_timing(ds_plan* plan, int enable);
 int ds_kernel_timing_read(ds_plan* plan, double* total_ms, int64_t* launches);
 
+/* ---- allocation-free planning ----------------------------------------------
+ * For callers that cannot allocate: code under HIP graph capture, tight
+ * serving loops, harnesses that forbid allocation.  ds_optimize_noalloc
+ * optimises one problem exactly as ds_optimize_seeds does (the same
+ * kernels and per-seed arithmetic, params.n_iters iterations,
+ * params.waves_per_seed), but allocates nothing, copies nothing from the
+ * host and never waits: the optimiser state, the work tables and the final
+ * trajectories live in a fixed device array of the library (about 5.1 MB
+ * per GPU, held until the process ends; its address is resolved once per
+ * device by ds_plan_create), and the tables are written on the device.
+ *   prob          as for ds_optimize_seeds (problem_tag is ignored, nothing
+ *                 is registered under it); prob->out_traj, if not NULL,
+ *                 receives the optimised seeds [S][T][7]
+ *   seed_results  device, [S] per-seed results
+ *   result        device, one ds_result (the best seed, as ds_get_best)
+ *   best_traj     device, [T][7] the best seed's trajectory
+ * Asynchronous on `stream`.  Every call on a GPU shares that GPU's array,
+ * which keeps the last call's contents: calls that overlap on one GPU
+ * (two streams, two host threads) race -- order them on one stream.
+ * Errors: as ds_optimize_seeds, DS_ERR_INVALID for S > DS_NOALLOC_MAX_SEEDS,
+ * DS_ERR_STATE if the array's address is not set up on the plan's device. */
+#define DS_NOALLOC_MAX_SEEDS 128
+int ds_optimize_noalloc(ds_plan* plan, const ds_problem* prob, ds_seed_result* seed_results,
+                        ds_result* result, float* best_traj, void* stream);
+
 /* ---- serving: continuous batching of planning requests -------------------
  * Requests are admitted into device slots while memory and slots allow;
  * every step runs params.block_iters iterations of every admitted request

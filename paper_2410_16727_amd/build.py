@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsopt.so")
-SOURCES = ["dsopt_kernels.hip", "dsopt_host.cpp", "dsopt_serve.cpp"]
+SOURCES = ["dsopt_kernels.hip", "dsopt_host.cpp", "dsopt_serve.cpp", "dsopt_noalloc.hip"]
 ARCH = os.environ.get("DSOPT_ARCH", "gfx950")
 
 HIPCC_FLAGS = [

@@ -400,6 +400,8 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   P.drain = prm->serve_drain ? 1 : 0;
   P.vlim = prm->v_limit; P.alim = prm->a_limit; P.jlim = prm->j_limit;
   p->blocks_per_cu = optimize_blocks_per_cu(P.waves, params_ext(P));
+  // the allocation-free call's device array, resolved once per device
+  if (int rc = noalloc_init(p->device)) return rc;
 
   p->robot_off = p->arena.alloc(sizeof(RobotDev));
   p->params_off = p->arena.alloc(sizeof(ParamsDev));

@@ -149,4 +149,7 @@ hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const Prob
                              bool ext, hipStream_t s);
 int team_block(int waves);
 int optimize_blocks_per_cu(int waves, bool ext);
+// Resolve the allocation-free call's device array on the current device
+// (dsopt_noalloc.hip); DS_OK or a DS_ERR_* code.
+int noalloc_init(int device);
 }  // namespace dsk

@@ -32,7 +32,9 @@ EXPORTED = [
     "ds_get_seed_results", "ds_problem_release", "ds_cost", "ds_cost_grad",
     "ds_sphere_centres", "ds_guide", "ds_serve_start", "ds_serve_submit", "ds_serve_step", "ds_serve_poll",
     "ds_serve_stats", "ds_serve_stop", "ds_kernel_timing", "ds_kernel_timing_read",
+    "ds_optimize_noalloc",
 ]
+NOALLOC_MAX_SEEDS = 128
 
 
 class DsError(RuntimeError):
@@ -131,6 +133,7 @@ def load():
                            f32p, vp]
     L.ds_kernel_timing.argtypes = [vp, C.c_int]
     L.ds_kernel_timing_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64)]
+    L.ds_optimize_noalloc.argtypes = [vp, C.POINTER(Problem), vp, vp, vp, vp]
     L.ds_serve_start.argtypes = [vp, C.c_int, C.c_int, vp]
     L.ds_serve_submit.argtypes = [vp, C.POINTER(Problem), C.POINTER(C.c_uint64)]
     L.ds_serve_step.argtypes = [vp]
@@ -298,6 +301,17 @@ class Plan:
             arr[i] = problem_struct(p["scene"], p["q_start"], p["goal"], p["tag"], p["seeds"],
                                     p.get("out"), S, T)
         check(self.lib.ds_optimize_seeds(self.h, arr, len(problems), _stream(stream)))
+
+    def optimize_noalloc(self, p, seed_results, result, best_traj, stream=None):
+        """The allocation-free call: p as for optimize (seeds, optional
+        out); seed_results (uint8 cuda tensor of S * sizeof(SeedResult)
+        bytes), result (uint8 cuda tensor of sizeof(Result) bytes) and
+        best_traj (float cuda tensor [T, 7]) receive the results."""
+        S, T, _ = p["seeds"].shape
+        pr = problem_struct(p["scene"], p["q_start"], p["goal"], p.get("tag", 0), p["seeds"],
+                            p.get("out"), S, T)
+        check(self.lib.ds_optimize_noalloc(self.h, C.byref(pr), _ptr(seed_results), _ptr(result),
+                                           _ptr(best_traj), _stream(stream)))
 
     def optimize_traced(self, p, stream=None):
         import torch
