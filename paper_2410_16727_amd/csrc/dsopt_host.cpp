@@ -262,23 +262,56 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
       td.push_back(t);
     }
   }
-  // longest tiles first: a tile's time grows with its group size (the
-  // spheres each lane walks), and the persistent grid drains the table in
-  // order, so the short tiles fill the tail instead of a long one starting
-  // last.  Per-seed arithmetic does not depend on the order.
-  if (n > 1)
-    std::stable_sort(td.begin(), td.end(),
-                     [](const TileDev& a, const TileDev& b) { return a.G > b.G; });
+  // Batched launches: one tile queue per XCD.  Problems go to the XCD with
+  // the least work so far, largest first (work ~ S T), so each problem's
+  // tiles -- and the records of its scene -- stay in one XCD's L2; inside a
+  // queue the longest tiles come first (a tile's time grows with its group
+  // size, and the short ones then fill the tail).  Per-seed arithmetic does
+  // not depend on the order.
+  std::vector<int> xcd_ranges;
+  if (n > 1) {
+    constexpr int NX = N_XCD;
+    std::vector<int> order(n), owner(n);
+    for (int i = 0; i < n; ++i) order[i] = i;
+    auto work = [&](int i) { return (long long)probs[i].n_seeds * probs[i].horizon; };
+    std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
+    long long load[NX] = {0};
+    for (int i : order) {
+      int best = 0;
+      for (int x = 1; x < NX; ++x)
+        if (load[x] < load[best]) best = x;
+      owner[i] = best;
+      load[best] += work(i);
+    }
+    std::stable_sort(td.begin(), td.end(), [&](const TileDev& a, const TileDev& b) {
+      if (owner[a.prob] != owner[b.prob]) return owner[a.prob] < owner[b.prob];
+      return a.G > b.G;
+    });
+    xcd_ranges.assign(NX + 1, 0);
+    for (const TileDev& t : td) xcd_ranges[owner[t.prob] + 1]++;
+    for (int x = 0; x < NX; ++x) xcd_ranges[x + 1] += xcd_ranges[x];
+  }
   uint8_t* tab = p->arena.ptr(launch->tab_off);
   ProbDev* pd_dev = reinterpret_cast<ProbDev*>(tab);
   size_t off_t = ((size_t)n * sizeof(ProbDev) + 255) / 256 * 256;
   TileDev* td_dev = reinterpret_cast<TileDev*>(tab + off_t);
   int* counter = reinterpret_cast<int*>(tab + off_t + ((size_t)total_tiles * sizeof(TileDev) + 255) / 256 * 256);
-  // problem and tile tables in one copy (they are adjacent in the arena)
+  // the tile-queue counters (N_XCD ints) and, for a batched launch, the
+  // queues' bounds after them
+  const size_t off_c = off_t + ((size_t)total_tiles * sizeof(TileDev) + 255) / 256 * 256;
+  const int* ranges_dev = xcd_ranges.empty() ? nullptr : counter + N_XCD;
+  // problem and tile tables (and the queue bounds) in one copy: they are
+  // adjacent in the arena
   {
-    std::vector<uint8_t> tabh(off_t + td.size() * sizeof(TileDev), 0);
+    std::vector<uint8_t> tabh(xcd_ranges.empty() ? off_t + td.size() * sizeof(TileDev)
+                                                 : off_c + N_XCD * sizeof(int) +
+                                                       xcd_ranges.size() * sizeof(int),
+                              0);
     std::memcpy(tabh.data(), pd.data(), n * sizeof(ProbDev));
     std::memcpy(tabh.data() + off_t, td.data(), td.size() * sizeof(TileDev));
+    if (!xcd_ranges.empty())
+      std::memcpy(tabh.data() + off_c + N_XCD * sizeof(int), xcd_ranges.data(),
+                  xcd_ranges.size() * sizeof(int));
     if (int rc = upload(p, tab, tabh.data(), tabh.size(), s)) return rc;
   }
   // fresh tiles (iteration counters and seed results start at zero) and an
@@ -294,7 +327,8 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   blocks = std::max(1, std::min(blocks, p->cu_count * p->blocks_per_cu));
   if (int rc = timed_launch(p, s, [&]() {
         return launch_optimize(p->robot_dev, p->params_dev, pd_dev, td_dev, total_tiles, counter,
-                               blocks, p->params.n_iters, W, params_ext(p->params), s);
+                               blocks, p->params.n_iters, W, params_ext(p->params), s,
+                               ranges_dev);
       }))
     return rc;
   HIP_TRY(launch_best(pd_dev, n, nullptr, s));

@@ -11,6 +11,7 @@ namespace dsk {
 constexpr int NJ = 7;
 constexpr int WAVE = 64;            // CDNA wavefront
 constexpr int WAVES_PER_BLOCK = 4;  // independent tiles per workgroup
+constexpr int N_XCD = 8;            // accelerator dies; workgroups are dealt to them in turn
 constexpr int BLOCK = WAVE * WAVES_PER_BLOCK;
 
 // Robot table, read with uniform (scalar) loads by every wavefront.
@@ -123,9 +124,12 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
                             hipStream_t s);
 hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
                          int cdz, uint16_t* out, hipStream_t s);
+// counter: N_XCD ints when xcd_ranges (N_XCD + 1 ints: the per-XCD queues'
+// bounds in the tile table) is given, else one.
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
-                           int max_iters, int waves, bool ext, hipStream_t s);
+                           int max_iters, int waves, bool ext, hipStream_t s,
+                           const int* xcd_ranges = nullptr);
 hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s);
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,
@@ -136,8 +140,8 @@ hipError_t launch_guide(const RobotDev* rb, const ParamsDev* pp, const ProbDev* 
 hipError_t launch_spheres(const RobotDev* rb, const float* X, int S, int T, float* out,
                           hipStream_t s);
 hipError_t launch_zero_i32(int* p, int n, hipStream_t s);
-// Fresh tiles (iteration counters, seed results) and the tile queue counter
-// (n_tiles >= 1).
+// Fresh tiles (iteration counters, seed results) and the tile queue
+// counters (N_XCD ints; n_tiles >= 1).
 hipError_t launch_tile_reset(const TileDev* tiles, const ProbDev* probs, int n_tiles, int* counter,
                              hipStream_t s);
 hipError_t launch_esdf_from_occupancy(const uint8_t* occ, int nx, int ny, int nz, float voxel,

@@ -223,15 +223,6 @@ __device__ __forceinline__ int block_of(const Sampler& S, float px, float py, fl
   return (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
 }
 
-// True when the coarse table proves the sample's hinge is zero: every
-// corner of every cell in the block is at least radius + eps (+ margin)
-// from the nearest obstacle, and a trilinear blend stays within its corner
-// range.
-__device__ __forceinline__ bool far_point(const Sampler& S, float px, float py, float pz, float r,
-                                          float far) {
-  return coarse_at(S, block_of(S, px, py, pz)) >= r + far;
-}
-
 // Trilinear blend of a cell record (a: z0 corners, b: z1 corners) and, with
 // GRAD, its spatial gradient.
 template <bool GRAD>
@@ -552,12 +543,12 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
       continue;
     }
     float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-    bool link_used = false;
     // chunks of CH spheres per lane (this lane takes every (W*L)-th sphere
-    // of the link): test each sample against the coarse table, locate its
-    // cell and issue its record loads only when the test cannot prove a
-    // zero hinge, then consume the chunk in sphere order -- CH gathers in
-    // flight per lane
+    // of the link): issue every record load of the chunk, then consume them
+    // in sphere order -- CH gathers in flight per lane.  A sample whose
+    // coarse block holds no node nearer than radius + eps (+ margin) has a
+    // zero hinge (a trilinear blend stays within its corners' range): it
+    // loads nothing.
     for (int s = s0; s < s1; s += LW * CH) {
       Cell cl[CH];
       float4 ra[CH], rz[CH];
@@ -573,16 +564,15 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
           cys[k] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
           czs[k] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
           rr[k] = sp.w;
-          if (SKIP && far_point(S, cxs[k], cys[k], czs[k], sp.w, P.far)) {
+          cl[k] = locate(S, cxs[k], cys[k], czs[k]);
+          if (SKIP && coarse_at(S, cl[k].cidx) >= sp.w + P.far) {
             use[k] = false;   // zero hinge, zero gradient
           } else {
-            cl[k] = locate(S, cxs[k], cys[k], czs[k]);
             ra[k] = load_rec(S, cl[k].off);
             rz[k] = load_rec(S, cl[k].off + 16);
             ++ng;
           }
         }
-        link_used |= use[k];
       }
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
@@ -591,9 +581,7 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
                             clr, FM);
       }
     }
-    // a link none of whose samples reached the hinge in this wavefront has
-    // a zero wrench everywhere: its projection would add zeros
-    if (GRAD && __any(link_used)) project(tw, l, FM, g);
+    if (GRAD) project(tw, l, FM, g);
   }
   if (PIPE) {
     // issue the record loads of the samples that can reach the hinge
@@ -1494,22 +1482,43 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
                          __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 
+// The next tile for this workgroup: from one atomic counter over the
+// whole table, or -- with per-XCD queues (xcd_ranges[x] .. xcd_ranges[x+1]
+// is queue x, counter[x] its position) -- from the queue of the XCD the
+// workgroup runs on (workgroups are dispatched to the 8 XCDs in turn), so
+// a problem's tiles, and its scene's records, stay in one XCD's L2; an
+// exhausted queue sends the workgroup on to the others.  -1: nothing left.
+__device__ __forceinline__ int next_tile(int* counter, const int* __restrict__ xcd_ranges,
+                                         int nt) {
+  if (!xcd_ranges) {
+    const int i = atomicAdd(counter, 1);
+    return i < nt ? i : -1;
+  }
+  const int home = (int)(blockIdx.x % N_XCD);
+  for (int q = 0; q < N_XCD; ++q) {
+    const int x = (home + q) % N_XCD;
+    const int b = xcd_ranges[x], len = xcd_ranges[x + 1] - b;
+    if (len <= 0) continue;
+    const int i = atomicAdd(&counter[x], 1);
+    if (i < len) return b + i;
+  }
+  return -1;
+}
+
 // Persistent optimiser: every team (W = 1: every wavefront) takes tiles
-// from an atomic counter until the table is exhausted (tile_list, if given,
-// indirects the table; n_tiles_dev, if given, overrides n_tiles).  Every
-// member of a team sees the same tile sequence and the same decisions, so
-// all of them reach every barrier.  Variants: TEAM (W > 1, history ring
-// in LDS) and EXT (self-collision and swept terms compiled in); the plain
-// variant carries no code for the optional terms.
-#ifndef DSOPT_WPE
-#define DSOPT_WPE 2
-#endif
+// (next_tile) until the table is exhausted (tile_list, if given, indirects
+// the table; n_tiles_dev, if given, overrides n_tiles).  Every member of a
+// team sees the same tile sequence and the same decisions, so all of them
+// reach every barrier.  Variants: TEAM (W > 1, history ring in LDS) and EXT
+// (self-collision and swept terms compiled in); the plain variant carries
+// no code for the optional terms.
 template <bool TEAM, bool EXT>
-__global__ void __launch_bounds__(TEAM ? MAX_TEAM * WAVE : BLOCK, TEAM ? 1 : DSOPT_WPE)
+__global__ void __launch_bounds__(TEAM ? MAX_TEAM * WAVE : BLOCK, TEAM ? 1 : 2)
 k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
            const ProbDev* __restrict__ probs, const TileDev* __restrict__ tiles,
            const int* __restrict__ tile_list, const int* __restrict__ n_tiles_dev, int n_tiles,
-           int* counter, int max_iters, const int* __restrict__ max_iters_dev) {
+           int* counter, int max_iters, const int* __restrict__ max_iters_dev,
+           const int* __restrict__ xcd_ranges) {
   extern __shared__ float s_dyn[];
   __shared__ int s_tile;
   stage_spheres(rb);
@@ -1525,18 +1534,18 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
   for (;;) {
     int mine = 0;
     if constexpr (TEAM) {
-      if (threadIdx.x == 0) s_tile = atomicAdd(counter, 1);
+      if (threadIdx.x == 0) s_tile = next_tile(counter, xcd_ranges, nt);
       __syncthreads();
       mine = s_tile;
       __syncthreads();
     } else {
-      // one increment per wavefront, by its first active lane, broadcast
-      // from that lane (correct for any set of active lanes)
+      // one fetch per wavefront, by its first active lane, broadcast from
+      // that lane (correct for any set of active lanes)
       const int first = __ffsll((long long)__ballot(1)) - 1;
-      if (lane == first) mine = atomicAdd(counter, 1);
+      if (lane == first) mine = next_tile(counter, xcd_ranges, nt);
       mine = __builtin_amdgcn_readfirstlane(__shfl(mine, first));
     }
-    if (mine >= nt) break;
+    if (mine < 0) break;
     const int ti = tile_list ? tile_list[mine] : mine;
     TileDev td = tiles[ti];
     if constexpr (TEAM) {
@@ -1545,9 +1554,10 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
                           s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS + COARSE_FLOATS);
       __syncthreads();   // the LDS ring is free for the next tile
     } else {
+      // this wavefront's coarse table (uniform)
+      const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
       run_tile<false, EXT>(rb, pp, probs, td, max_iters, tm, nullptr,
-                           reinterpret_cast<uint16_t*>(s_dyn + (threadIdx.x / WAVE) * COARSE_FLOATS),
-                           nullptr);
+                           reinterpret_cast<uint16_t*>(s_dyn + wv * COARSE_FLOATS), nullptr);
     }
   }
 }
@@ -1618,7 +1628,7 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
 __global__ void __launch_bounds__(64) k_tile_reset(const TileDev* __restrict__ tiles,
                                                    const ProbDev* __restrict__ probs,
                                                    int* __restrict__ counter) {
-  if (blockIdx.x == 0 && threadIdx.x == 0) *counter = 0;   // the tile queue
+  if (blockIdx.x == 0 && threadIdx.x < N_XCD) counter[threadIdx.x] = 0;   // the tile queues
   const TileDev td = tiles[blockIdx.x];
   reinterpret_cast<int*>(td.state)[ST_ITER + threadIdx.x] = 0;
   constexpr int W = (int)(sizeof(ds_seed_result) / sizeof(int));
@@ -1920,7 +1930,7 @@ size_t team_lds(int W) {
 }
 
 using OptKernel = void (*)(const RobotDev*, const ParamsDev*, const ProbDev*, const TileDev*,
-                           const int*, const int*, int, int*, int, const int*);
+                           const int*, const int*, int, int*, int, const int*, const int*);
 
 static OptKernel optimize_kernel(int W, bool ext) {
   if (W > 1) return ext ? k_optimize<true, true> : k_optimize<true, false>;
@@ -1929,10 +1939,12 @@ static OptKernel optimize_kernel(int W, bool ext) {
 
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
-                           int max_iters, int W, bool ext, hipStream_t s) {
+                           int max_iters, int W, bool ext, hipStream_t s,
+                           const int* xcd_ranges) {
   hipLaunchKernelGGL(optimize_kernel(W, ext), dim3(grid_blocks), dim3(team_block(W)),
                      team_lds(W), s, rb, pp, probs, tiles, (const int*)nullptr,
-                     (const int*)nullptr, n_tiles, counter, max_iters, (const int*)nullptr);
+                     (const int*)nullptr, n_tiles, counter, max_iters, (const int*)nullptr,
+                     xcd_ranges);
   return hipGetLastError();
 }
 
@@ -1944,7 +1956,7 @@ hipError_t launch_serve_step(const RobotDev* rb, const ParamsDev* pp, const Prob
   // iterations of this replay are read from max_iters_dev
   hipLaunchKernelGGL(optimize_kernel(W, ext), dim3(grid_blocks), dim3(team_block(W)),
                      team_lds(W), s, rb, pp, probs, tiles, tile_list + 1, tile_list, max_tiles,
-                     counter, 0, max_iters_dev);
+                     counter, 0, max_iters_dev, (const int*)nullptr);
   return hipGetLastError();
 }
 
