@@ -132,6 +132,29 @@ def test_full_batched_workload_flags_vs_oracle(batchD):
     say(f"checked {n_checked} sampled seeds")
 
 
+def test_full_batch_equals_plain(batchD):
+    """The full batch (more tiles than the chip holds at once, spread over
+    the per-XCD queues): every sampled seed comes out bitwise as in a
+    launch of its problem alone, its counters included."""
+    plan, probs, seeds = batchD["plan"], batchD["probs"], batchD["seeds"]
+    outs_b = [torch.zeros_like(s) for s in seeds]
+    say("full batch vs plain")
+    plan.optimize([spec(p, seeds[i], 900 + i, outs_b[i]) for i, p in enumerate(probs)])
+    heavy = sorted(range(len(probs)), key=lambda i: -probs[i].S * probs[i].T)[:3]
+    for i in sorted(set(heavy + [0, 17, 33, 48, 63])):
+        p = probs[i]
+        out_p = torch.zeros_like(seeds[i])
+        plan.optimize([spec(p, seeds[i], 1000 + i, out_p)])
+        torch.cuda.synchronize()
+        assert torch.equal(outs_b[i], out_p), (i, p.S, p.T)
+        rb, rp = plan.seed_results(900 + i, p.S), plan.seed_results(1000 + i, p.S)
+        for k in rb:
+            assert np.array_equal(rb[k], rp[k], equal_nan=rb[k].dtype.kind == "f"), (i, k)
+        plan.release(1000 + i)
+    for i in range(len(probs)):
+        plan.release(900 + i)
+
+
 @pytest.mark.parametrize("waves,m", [(1, 8), (8, 8), (8, 3), (2, 5)])
 def test_serving_matches_alone_bitwise(waves, m):
     """Served in 7-iteration blocks (every request resumes in later
