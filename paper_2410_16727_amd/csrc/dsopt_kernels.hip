@@ -65,10 +65,25 @@ constexpr int DPP_QUAD_XOR2 = 0x4E;   // quad_perm [2,3,0,1]
 constexpr int DPP_HALF_MIRROR = 0x141;
 constexpr int DPP_MIRROR = 0x140;
 
+constexpr int DPP_WAVE_SHL1 = 0x130;   // lane i reads lane i + 1
+constexpr int DPP_WAVE_SHR1 = 0x138;   // lane i reads lane i - 1
+
 template <int CTRL>
 __device__ __forceinline__ float dpp(float v) {
   return __int_as_float(
       __builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+// The value of lane i + 1 / lane i - 1 (one DPP move; the lane past either
+// end of the wavefront reads 0).  Callers only use lanes whose neighbour is
+// in the same lane group.
+__device__ __forceinline__ float from_next(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), DPP_WAVE_SHL1, 0xF, 0xF, true));
+}
+__device__ __forceinline__ float from_prev(float v) {
+  return __int_as_float(
+      __builtin_amdgcn_update_dpp(0, __float_as_int(v), DPP_WAVE_SHR1, 0xF, 0xF, true));
 }
 
 // The value of lane ^ 16 (v_permlane16_swap exchanges the odd rows of its
@@ -188,9 +203,10 @@ __device__ __forceinline__ Cell locate(const Sampler& S, float px, float py, flo
   float ux = (px - S.ox) * S.inv_h;
   float uy = (py - S.oy) * S.inv_h;
   float uz = (pz - S.oz) * S.inv_h;
-  float cx = fminf(fmaxf(ux, 0.f), S.nxm1);
-  float cy = fminf(fmaxf(uy, 0.f), S.nym1);
-  float cz = fminf(fmaxf(uz, 0.f), S.nzm1);
+  // clamp into [0, n-1] (one v_med3 each)
+  float cx = __builtin_amdgcn_fmed3f(ux, 0.f, S.nxm1);
+  float cy = __builtin_amdgcn_fmed3f(uy, 0.f, S.nym1);
+  float cz = __builtin_amdgcn_fmed3f(uz, 0.f, S.nzm1);
   c.mx = (cx == ux) ? S.inv_h : 0.f;
   c.my = (cy == uy) ? S.inv_h : 0.f;
   c.mz = (cz == uz) ? S.inv_h : 0.f;
@@ -203,10 +219,15 @@ __device__ __forceinline__ Cell locate(const Sampler& S, float px, float py, flo
   c.fx = ux - (float)ix;
   c.fy = uy - (float)iy;
   c.fz = uz - (float)iz;
-  // record index ix + cx*(iy + cy*iz); every factor fits 24 bits
+  // record index ix + cx*(iy + cy*iz); every factor fits 24 bits: the
+  // upload keeps (ny-1)(nz-1) below 2^24, and the coarse table has at most
+  // COARSE_MAX blocks (stating the bounds keeps both products 24-bit
+  // multiply-adds)
   unsigned row = __umul24((unsigned)S.cy, (unsigned)iz) + (unsigned)iy;
+  __builtin_assume(row < (1u << 24));
   c.off = (int)((__umul24((unsigned)S.cx, row) + (unsigned)ix) << 5);
   unsigned crow = __umul24((unsigned)S.cdy, (unsigned)(iz >> S.cshift)) + (unsigned)(iy >> S.cshift);
+  __builtin_assume(crow < (1u << 24));
   c.cidx = (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
   return c;
 }
@@ -215,11 +236,12 @@ __device__ __forceinline__ Cell locate(const Sampler& S, float px, float py, flo
 // for u >= 0, min(trunc(min(u, n-1)), n-2) == trunc(min(u, n-2)), so the
 // block index is the same with a third of the arithmetic.
 __device__ __forceinline__ int block_of(const Sampler& S, float px, float py, float pz) {
-  const int ix = (int)fminf(fmaxf((px - S.ox) * S.inv_h, 0.f), S.fxm2);
-  const int iy = (int)fminf(fmaxf((py - S.oy) * S.inv_h, 0.f), S.fym2);
-  const int iz = (int)fminf(fmaxf((pz - S.oz) * S.inv_h, 0.f), S.fzm2);
+  const int ix = (int)__builtin_amdgcn_fmed3f((px - S.ox) * S.inv_h, 0.f, S.fxm2);
+  const int iy = (int)__builtin_amdgcn_fmed3f((py - S.oy) * S.inv_h, 0.f, S.fym2);
+  const int iz = (int)__builtin_amdgcn_fmed3f((pz - S.oz) * S.inv_h, 0.f, S.fzm2);
   const unsigned crow =
       __umul24((unsigned)S.cdy, (unsigned)(iz >> S.cshift)) + (unsigned)(iy >> S.cshift);
+  __builtin_assume(crow < (1u << 24));
   return (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
 }
 
@@ -293,28 +315,29 @@ struct EvalOut {
 // a_t = v_t - v_{t-1} (t < T), j_t = a_{t+1} - a_t (t < T) plus
 // j_{-1} = a_0 at t = 0 -- the first/second/third differences of the
 // sequence padded with two copies of q_0 and of q_{T-1}.  The gradient
-// applies the transposed stencils with the same shuffles.
+// applies the transposed stencils with the same lane shifts (DPP moves; the
+// masks keep every read inside the lane group).
 template <bool GRAD>
 __device__ __forceinline__ float smoothness(const ParamsDev& P, const float* q, int t, int T,
                                             float* g) {
   float c = 0.f;
 #pragma unroll
   for (int j = 0; j < NJ; ++j) {
-    float qn = __shfl_down(q[j], 1);
+    float qn = from_next(q[j]);
     float v = (t <= T - 2) ? qn - q[j] : 0.f;
-    float vp = __shfl_up(v, 1);
+    float vp = from_prev(v);
     float a = (t < T) ? v - (t >= 1 ? vp : 0.f) : 0.f;
-    float an = __shfl_down(a, 1);
+    float an = from_next(a);
     float jk = (t < T) ? ((t + 1 < T ? an : 0.f) - a) : 0.f;
     float jm = (t == 0) ? a : 0.f;   // j_{-1}
     c += P.lv * (v * v) + P.la * (a * a) + P.lj * (jk * jk) + P.lj * (jm * jm);
     if (GRAD) {
       float jb = 2.f * P.lj * jk;
-      float jbp = __shfl_up(jb, 1);
+      float jbp = from_prev(jb);
       float ab = (t < T) ? 2.f * P.la * a + ((t == 0) ? 2.f * P.lj * jm : jbp) - jb : 0.f;
-      float abn = __shfl_down(ab, 1);
+      float abn = from_next(ab);
       float vb = (t <= T - 2) ? 2.f * P.lv * v + ab - abn : 0.f;
-      float vbp = __shfl_up(vb, 1);
+      float vbp = from_prev(vb);
       g[j] += ((t >= 1) ? vbp : 0.f) - vb;
     }
   }
@@ -895,8 +918,36 @@ struct Hist {
     h[H_YY + k * WAVE + lane] = q;
   }
 };
-using GHist = Hist<DS_GLOBAL float*>;
 using LHist = Hist<float*>;
+
+// The ring in the tile state, read and written through a buffer resource:
+// the lane's column is the vector offset and slot and joint a scalar one,
+// so an access needs no per-lane 64-bit address arithmetic.  Slots are
+// wave-uniform (one seed per wavefront).
+struct BHist {
+  __amdgpu_buffer_rsrc_t r;
+  int vo;   // lane * 4
+  __device__ __forceinline__ float ld(int idx) const {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, idx * 4, 0));
+  }
+  __device__ __forceinline__ void st(int idx, float v) const {
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vo, idx * 4, 0);
+  }
+  __device__ __forceinline__ float s(int k, int j) const { return ld(H_S + (k * NJ + j) * WAVE); }
+  __device__ __forceinline__ float y(int k, int j) const { return ld(H_Y + (k * NJ + j) * WAVE); }
+  __device__ __forceinline__ float rho(int k) const { return ld(H_RHO + k * WAVE); }
+  __device__ __forceinline__ float yy(int k) const { return ld(H_YY + k * WAVE); }
+  __device__ __forceinline__ void push(int k, const float* sv, const float* yv, float r, float q) const {
+    k = __builtin_amdgcn_readfirstlane(k);
+#pragma unroll
+    for (int j = 0; j < NJ; ++j) {
+      st(H_S + (k * NJ + j) * WAVE, sv[j]);
+      st(H_Y + (k * NJ + j) * WAVE, yv[j]);
+    }
+    st(H_RHO + k * WAVE, r);
+    st(H_YY + k * WAVE, q);
+  }
+};
 
 // Steepest-descent step scaled so that its largest entry is delta0 (the
 // restart direction).
@@ -1324,11 +1375,11 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
   }
   int n_left = min(max_iters, n_iters - iter);
   // the history ring: LDS copy for a team, else the tile state
-  typename std::conditional<LDS_HIST, LHist, GHist>::type hist;
-  hist.lane = c.lane;
+  typename std::conditional<LDS_HIST, LHist, BHist>::type hist;
   // the scene's coarse table: shared by the team, else this wavefront's own
   c.S.cm = lds(coarse_lds);
   if constexpr (LDS_HIST) {
+    hist.lane = c.lane;
     hist.h = hist_lds;
     if (iter > 0 && n_left > 0) {   // resume: bring the ring into LDS
       const DS_GLOBAL float* src = c.st + ST_RHO;
@@ -1340,7 +1391,9 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
     // barrier)
     if (iter > 0 && n_left > 0) team_rebuild_products(c, hist, tm, cnt, head, lds(dir_lds));
   } else {
-    hist.h = c.st + ST_RHO;
+    hist.r = __builtin_amdgcn_make_buffer_rsrc((void*)(float*)(c.st + ST_RHO), (short)0,
+                                               (int)(H_FLOATS * sizeof(float)), RSRC_DWORD3);
+    hist.vo = c.lane * 4;
     // one wavefront: its LDS accesses complete in order, no barrier needed
     if (c.P.skip) stage_coarse(pb.sc, lds(coarse_lds), c.lane, WAVE);
   }
