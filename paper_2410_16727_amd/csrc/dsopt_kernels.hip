@@ -923,20 +923,31 @@ using LHist = Hist<float*>;
 // The ring in the tile state, read and written through a buffer resource:
 // the lane's column is the vector offset and slot and joint a scalar one,
 // so an access needs no per-lane 64-bit address arithmetic.  Slots are
-// wave-uniform (one seed per wavefront).
+// wave-uniform (one seed per wavefront).  Only the first copy's lanes that
+// hold a waypoint touch memory for s and y: the other copies read the first
+// copy's column (the same bits: every copy carries the same s and y), and
+// lanes past the horizon (s = y = 0 there) use an offset past the end of
+// the buffer, which reads zeros and drops stores without a memory access.
+// rho and y^T y, the same in every lane, are read by all lanes from column
+// 0 (one broadcast access).
+constexpr int HIST_OFF_NONE = 0x7FFFFF00;
 struct BHist {
   __amdgpu_buffer_rsrc_t r;
-  int vo;   // lane * 4
+  int vo;   // column * 4 for loads, or HIST_OFF_NONE
+  int vw;   // column * 4 for stores (first copy only), or HIST_OFF_NONE
   __device__ __forceinline__ float ld(int idx) const {
     return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, vo, idx * 4, 0));
   }
+  __device__ __forceinline__ float ld0(int idx) const {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, 0, idx * 4, 0));
+  }
   __device__ __forceinline__ void st(int idx, float v) const {
-    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vo, idx * 4, 0);
+    __builtin_amdgcn_raw_buffer_store_b32(__float_as_uint(v), r, vw, idx * 4, 0);
   }
   __device__ __forceinline__ float s(int k, int j) const { return ld(H_S + (k * NJ + j) * WAVE); }
   __device__ __forceinline__ float y(int k, int j) const { return ld(H_Y + (k * NJ + j) * WAVE); }
-  __device__ __forceinline__ float rho(int k) const { return ld(H_RHO + k * WAVE); }
-  __device__ __forceinline__ float yy(int k) const { return ld(H_YY + k * WAVE); }
+  __device__ __forceinline__ float rho(int k) const { return ld0(H_RHO + k * WAVE); }
+  __device__ __forceinline__ float yy(int k) const { return ld0(H_YY + k * WAVE); }
   __device__ __forceinline__ void push(int k, const float* sv, const float* yv, float r, float q) const {
     k = __builtin_amdgcn_readfirstlane(k);
 #pragma unroll
@@ -1393,7 +1404,8 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
   } else {
     hist.r = __builtin_amdgcn_make_buffer_rsrc((void*)(float*)(c.st + ST_RHO), (short)0,
                                                (int)(H_FLOATS * sizeof(float)), RSRC_DWORD3);
-    hist.vo = c.lane * 4;
+    hist.vo = c.active ? (c.lane & (c.G - 1)) * 4 : HIST_OFF_NONE;
+    hist.vw = (c.active && c.lane < c.G) ? c.lane * 4 : HIST_OFF_NONE;
     // one wavefront: its LDS accesses complete in order, no barrier needed
     if (c.P.skip) stage_coarse(pb.sc, lds(coarse_lds), c.lane, WAVE);
   }
