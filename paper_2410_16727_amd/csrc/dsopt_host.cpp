@@ -209,8 +209,11 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   auto launch = std::make_shared<LaunchRec>();
   int total_tiles = 0;
   for (int i = 0; i < n; ++i) total_tiles += tiles_for(probs[i].n_seeds, probs[i].horizon);
+  // tables: problems, tiles, the queue counters and bounds (256 B), the
+  // ordered queues (one int per tile), landing records
   const size_t land_at = ((size_t)n * sizeof(ProbDev) + 255) / 256 * 256 +
-                         ((size_t)total_tiles * sizeof(TileDev) + 255) / 256 * 256 + 256;
+                         ((size_t)total_tiles * sizeof(TileDev) + 255) / 256 * 256 + 256 +
+                         ((size_t)total_tiles * sizeof(int) + 255) / 256 * 256;
   size_t tab_bytes = land_at + (size_t)n * LAND_BYTES;
   launch->tab_off = arena_alloc(p, tab_bytes);
   if (launch->tab_off == SIZE_MAX) return fail(DS_ERR_NOMEM, "arena full (tables)");
@@ -325,10 +328,26 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
   const int per_block = W > 1 ? 1 : WAVES_PER_BLOCK;
   int blocks = (total_tiles + per_block - 1) / per_block;
   blocks = std::max(1, std::min(blocks, p->cu_count * p->blocks_per_cu));
+  // A batched launch with more tiles than resident wavefronts (or teams)
+  // first runs every tile's initial evaluation, then orders each queue
+  // longest expected tile first (lane group, then cost at the seed) and
+  // runs the iterations: the long seeds start in the first round instead
+  // of the tail.  A seed resumes exactly where the initial launch left it.
+  const int slots = p->cu_count * p->blocks_per_cu * per_block;
+  const bool ordered = !xcd_ranges.empty() && total_tiles > slots && p->params.n_iters > 0;
+  int* list_dev = counter + 64;   // after the 256-byte counter slot
   if (int rc = timed_launch(p, s, [&]() {
+        if (ordered) {
+          hipError_t e = launch_optimize(p->robot_dev, p->params_dev, pd_dev, td_dev, total_tiles,
+                                         counter, blocks, 0, W, params_ext(p->params), s,
+                                         ranges_dev);
+          if (e != hipSuccess) return e;
+          e = launch_queue_order(td_dev, ranges_dev, list_dev, counter, s);
+          if (e != hipSuccess) return e;
+        }
         return launch_optimize(p->robot_dev, p->params_dev, pd_dev, td_dev, total_tiles, counter,
                                blocks, p->params.n_iters, W, params_ext(p->params), s,
-                               ranges_dev);
+                               ranges_dev, ordered ? list_dev : nullptr);
       }))
     return rc;
   HIP_TRY(launch_best(pd_dev, n, nullptr, s));

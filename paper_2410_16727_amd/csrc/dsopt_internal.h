@@ -126,10 +126,18 @@ hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, i
                          int cdz, uint16_t* out, hipStream_t s);
 // counter: N_XCD ints when xcd_ranges (N_XCD + 1 ints: the per-XCD queues'
 // bounds in the tile table) is given, else one.
+// tile_list (optional): the queue order, a permutation of 0..n_tiles-1.
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
                            int max_iters, int waves, bool ext, hipStream_t s,
-                           const int* xcd_ranges = nullptr);
+                           const int* xcd_ranges = nullptr, const int* tile_list = nullptr);
+// Order each per-XCD queue (xcd_ranges: N_XCD + 1 ints) longest expected
+// tile first -- larger lane groups first, then higher cost at the seed (the
+// tile state's J after the initial evaluation) -- into list (a permutation
+// of the tile table inside each queue's range), and empty the queue
+// counters.
+hipError_t launch_queue_order(const TileDev* tiles, const int* xcd_ranges, int* list,
+                              int* counter, hipStream_t s);
 hipError_t launch_best(const ProbDev* probs, int n_probs, const int* list, hipStream_t s);
 hipError_t launch_cost(const RobotDev* rb, const ParamsDev* pp, const ProbDev* prob,
                        const float* X, int S, int T, const float* dJ, float* J_out, float* dX,

@@ -1360,7 +1360,9 @@ __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const 
   int ngath = 0;   // cell records gathered by this lane in this launch
   int iter = sti[ST_ITER + c.lane];
   int phase;
-  if (iter == 0) {
+  // a tile whose initial evaluation ran in an earlier launch (iteration 0,
+  // one gradient evaluation counted) resumes from its state like any other
+  if (iter == 0 && sti[ST_EVG + c.lane] == 0) {
     if (c.active) {
       const DS_GLOBAL float* sp = glb(pb.seeds) + ((size_t)c.seed * c.T + c.t) * NJ;
 #pragma unroll
@@ -1690,12 +1692,55 @@ __global__ void __launch_bounds__(256) k_best(const ProbDev* __restrict__ probs,
 // Fresh tiles: each tile's iteration counters (so the optimiser starts from
 // the seed) and its seed's result record (counters accumulate over
 // launches).  One workgroup of one wavefront per tile.
+// Queue order of a batched launch after the tiles' initial evaluation: one
+// workgroup per XCD queue sorts its tiles, longest expected first -- by
+// lane group (a G = 64 tile walks twice the spheres per lane of a G = 32
+// one), then by the cost at the seed (seeds far from a good trajectory
+// tend to need more line-search candidates) -- with a counting sort over
+// ORDER_BINS keys.  Ties land in any order: the order only decides when a
+// seed runs, never what it computes.
+constexpr int ORDER_BINS = 4096;
+constexpr int ORDER_THREADS = 1024;
+__device__ __forceinline__ int order_key(const TileDev& t) {
+  const float J = t.state[ST_J];
+  const int grp = t.G >= 64 ? 2 : (t.G >= 32 ? 1 : 0);
+  // log2(1 + J) in 1/48 steps, 1024 per group; a NaN cost sorts last
+  const float l = J > 0.f ? __log2f(1.f + J) * 48.f : 0.f;
+  const int b = l >= 0.f ? (int)fminf(l, 1023.f) : 0;
+  return grp * 1024 + b;
+}
+__global__ void __launch_bounds__(ORDER_THREADS) k_queue_order(const TileDev* __restrict__ tiles,
+                                                               const int* __restrict__ ranges,
+                                                               int* __restrict__ list,
+                                                               int* __restrict__ counter) {
+  __shared__ int bins[ORDER_BINS];
+  const int x = blockIdx.x;
+  const int b = ranges[x], e = ranges[x + 1];
+  for (int i = threadIdx.x; i < ORDER_BINS; i += blockDim.x) bins[i] = 0;
+  if (threadIdx.x == 0) counter[x] = 0;
+  __syncthreads();
+  for (int i = b + threadIdx.x; i < e; i += blockDim.x) atomicAdd(&bins[order_key(tiles[i])], 1);
+  __syncthreads();
+  if (threadIdx.x == 0) {   // start of each key's run, largest key first
+    int run = 0;
+    for (int k = ORDER_BINS - 1; k >= 0; --k) {
+      const int c = bins[k];
+      bins[k] = run;
+      run += c;
+    }
+  }
+  __syncthreads();
+  for (int i = b + threadIdx.x; i < e; i += blockDim.x)
+    list[b + atomicAdd(&bins[order_key(tiles[i])], 1)] = i;
+}
+
 __global__ void __launch_bounds__(64) k_tile_reset(const TileDev* __restrict__ tiles,
                                                    const ProbDev* __restrict__ probs,
                                                    int* __restrict__ counter) {
   if (blockIdx.x == 0 && threadIdx.x < N_XCD) counter[threadIdx.x] = 0;   // the tile queues
   const TileDev td = tiles[blockIdx.x];
   reinterpret_cast<int*>(td.state)[ST_ITER + threadIdx.x] = 0;
+  reinterpret_cast<int*>(td.state)[ST_EVG + threadIdx.x] = 0;
   constexpr int W = (int)(sizeof(ds_seed_result) / sizeof(int));
   if (threadIdx.x < W)
     reinterpret_cast<int*>(probs[td.prob].seed_res + td.seed0)[threadIdx.x] = 0;
@@ -2005,11 +2050,17 @@ static OptKernel optimize_kernel(int W, bool ext) {
 hipError_t launch_optimize(const RobotDev* rb, const ParamsDev* pp, const ProbDev* probs,
                            const TileDev* tiles, int n_tiles, int* counter, int grid_blocks,
                            int max_iters, int W, bool ext, hipStream_t s,
-                           const int* xcd_ranges) {
+                           const int* xcd_ranges, const int* tile_list) {
   hipLaunchKernelGGL(optimize_kernel(W, ext), dim3(grid_blocks), dim3(team_block(W)),
-                     team_lds(W), s, rb, pp, probs, tiles, (const int*)nullptr,
-                     (const int*)nullptr, n_tiles, counter, max_iters, (const int*)nullptr,
-                     xcd_ranges);
+                     team_lds(W), s, rb, pp, probs, tiles, tile_list, (const int*)nullptr,
+                     n_tiles, counter, max_iters, (const int*)nullptr, xcd_ranges);
+  return hipGetLastError();
+}
+
+hipError_t launch_queue_order(const TileDev* tiles, const int* xcd_ranges, int* list,
+                              int* counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_queue_order, dim3(N_XCD), dim3(ORDER_THREADS), 0, s, tiles, xcd_ranges,
+                     list, counter);
   return hipGetLastError();
 }
 

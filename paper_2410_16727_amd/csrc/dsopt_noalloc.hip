@@ -58,6 +58,7 @@ __global__ void __launch_bounds__(64) k_noalloc_setup(ProbDev pd, uint8_t* base)
     }
   }
   reinterpret_cast<int*>(state)[ST_ITER + threadIdx.x] = 0;
+  reinterpret_cast<int*>(state)[ST_EVG + threadIdx.x] = 0;
   constexpr int W = (int)(sizeof(ds_seed_result) / sizeof(int));
   if (threadIdx.x < W) reinterpret_cast<int*>(pd.seed_res + k)[threadIdx.x] = 0;
 }
