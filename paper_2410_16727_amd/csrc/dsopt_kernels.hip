@@ -245,29 +245,38 @@ __device__ __forceinline__ int block_of(const Sampler& S, float px, float py, fl
   return (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
 }
 
-// Trilinear blend of a cell record (a: z0 corners, b: z1 corners) and, with
-// GRAD, its spatial gradient.
-template <bool GRAD>
-__device__ __forceinline__ float blend(const Sampler& S, const Cell& c, float4 a, float4 b,
-                                       float& gx, float& gy, float& gz) {
-  float dx00 = a.y - a.x, dx10 = a.w - a.z, dx01 = b.y - b.x, dx11 = b.w - b.z;
-  float c00 = a.x + c.fx * dx00;
-  float c10 = a.z + c.fx * dx10;
-  float c01 = b.x + c.fx * dx01;
-  float c11 = b.z + c.fx * dx11;
-  float dy0 = c10 - c00, dy1 = c11 - c01;
-  float c0 = c00 + c.fy * dy0;
-  float c1 = c01 + c.fy * dy1;
-  float dz = c1 - c0;
-  float d = c0 + c.fz * dz;
-  if (GRAD) {
-    float e0 = dx00 + c.fy * (dx10 - dx00);
-    float e1 = dx01 + c.fy * (dx11 - dx01);
-    gx = (e0 + c.fz * (e1 - e0)) * c.mx;
-    gy = (dy0 + c.fz * (dy1 - dy0)) * c.my;
-    gz = dz * c.mz;
-  }
-  return d;
+// Trilinear blend of a cell record (a: z0 corners, b: z1 corners): the
+// value, and the differences its spatial gradient is formed from.
+struct Blend {
+  float d;                          // interpolated distance
+  float dx00, dx10, dx01, dx11;     // x differences of the four x edges
+  float dy0, dy1, dz;               // y differences at z0/z1, z difference
+};
+
+__device__ __forceinline__ Blend blend_value(const Cell& c, float4 a, float4 b) {
+  Blend r;
+  r.dx00 = a.y - a.x; r.dx10 = a.w - a.z; r.dx01 = b.y - b.x; r.dx11 = b.w - b.z;
+  float c00 = a.x + c.fx * r.dx00;
+  float c10 = a.z + c.fx * r.dx10;
+  float c01 = b.x + c.fx * r.dx01;
+  float c11 = b.z + c.fx * r.dx11;
+  r.dy0 = c10 - c00;
+  r.dy1 = c11 - c01;
+  float c0 = c00 + c.fy * r.dy0;
+  float c1 = c01 + c.fy * r.dy1;
+  r.dz = c1 - c0;
+  r.d = c0 + c.fz * r.dz;
+  return r;
+}
+
+// Its spatial gradient (zero along axes where the point was clamped).
+__device__ __forceinline__ void blend_grad(const Cell& c, const Blend& r, float& gx, float& gy,
+                                           float& gz) {
+  float e0 = r.dx00 + c.fy * (r.dx10 - r.dx00);
+  float e1 = r.dx01 + c.fy * (r.dx11 - r.dx01);
+  gx = (e0 + c.fz * (e1 - e0)) * c.mx;
+  gy = (r.dy0 + c.fz * (r.dy1 - r.dy0)) * c.my;
+  gz = r.dz * c.mz;
 }
 
 __device__ __forceinline__ float4 load_rec(const Sampler& S, int off) {
@@ -368,15 +377,19 @@ __device__ __forceinline__ void sphere_term(const ParamsDev& P, const Sampler& S
                                             float4 ra, float4 rz, float r, float cx, float cy,
                                             float cz, float& phisum, float& clr, float* FM) {
   constexpr bool GRAD = (MODE == EV_GRAD);
-  float gx, gy, gz;
-  float d = blend<GRAD>(S, cl, ra, rz, gx, gy, gz);
-  float D = d - r;
+  const Blend bl = blend_value(cl, ra, rz);
+  float D = bl.d - r;
   float De = D - P.eps;
   float phi = (D < P.eps) ? De * De * P.half_inv_eps : 0.f;
   phi = (D < 0.f) ? 0.5f * P.eps - D : phi;
   phisum += phi;
   if (MODE == EV_RESULT) clr = fminf(clr, D);
-  if (GRAD) {
+  // the force is zero outside the hinge band: when no lane of the
+  // wavefront has a sample inside it, the gradient and the wrench terms
+  // (which would add zeros) are skipped
+  if (GRAD && __any(D < P.eps)) {
+    float gx, gy, gz;
+    blend_grad(cl, bl, gx, gy, gz);
     float dphi = (D < P.eps) ? De * P.inv_eps : 0.f;
     dphi = (D < 0.f) ? -1.f : dphi;
     float w = P.wc * dphi;
