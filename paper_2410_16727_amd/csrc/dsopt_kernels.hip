@@ -371,9 +371,10 @@ struct Team {
 };
 
 // Hinge cost of one sphere sample and, with GRAD, its force accumulated into
-// the link wrench (F, M about the world origin).
+// the link wrench (F, M about the world origin).  Returns whether the force
+// terms ran (some lane of the wavefront inside the hinge band).
 template <int MODE>
-__device__ __forceinline__ void sphere_term(const ParamsDev& P, const Sampler& S, const Cell& cl,
+__device__ __forceinline__ bool sphere_term(const ParamsDev& P, const Sampler& S, const Cell& cl,
                                             float4 ra, float4 rz, float r, float cx, float cy,
                                             float cz, float& phisum, float& clr, float* FM) {
   constexpr bool GRAD = (MODE == EV_GRAD);
@@ -387,7 +388,8 @@ __device__ __forceinline__ void sphere_term(const ParamsDev& P, const Sampler& S
   // the force is zero outside the hinge band: when no lane of the
   // wavefront has a sample inside it, the gradient and the wrench terms
   // (which would add zeros) are skipped
-  if (GRAD && __any(D < P.eps)) {
+  const bool band = GRAD && __any(D < P.eps);
+  if (band) {
     float gx, gy, gz;
     blend_grad(cl, bl, gx, gy, gz);
     float dphi = (D < P.eps) ? De * P.inv_eps : 0.f;
@@ -399,6 +401,7 @@ __device__ __forceinline__ void sphere_term(const ParamsDev& P, const Sampler& S
     FM[4] += cz * fx - cx * fz;
     FM[5] += cx * fy - cy * fx;
   }
+  return band;
 }
 
 // Project a link wrench on the joints 0..l: g_i += z_i . (M - o_i x F).
@@ -579,6 +582,7 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
       continue;
     }
     float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    bool forced = false;   // some sample of this link added a force
     // chunks of CH spheres per lane (this lane takes every (W*L)-th sphere
     // of the link): issue every record load of the chunk, then consume them
     // in sphere order -- CH gathers in flight per lane.  A sample whose
@@ -613,11 +617,13 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         if (use[k])
-          sphere_term<MODE>(P, S, cl[k], ra[k], rz[k], rr[k], cxs[k], cys[k], czs[k], phisum,
-                            clr, FM);
+          forced |= sphere_term<MODE>(P, S, cl[k], ra[k], rz[k], rr[k], cxs[k], cys[k], czs[k],
+                                      phisum, clr, FM);
       }
     }
-    if (GRAD) project(tw, l, FM, g);
+    // a link with no force in this wavefront has a zero wrench everywhere:
+    // its projection would add zeros
+    if (GRAD && __any(forced)) project(tw, l, FM, g);
   }
   if (PIPE) {
     // issue the record loads of the samples that can reach the hinge
@@ -637,14 +643,15 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
 #pragma unroll
     for (int l = 0; l < NJ; ++l) {
       float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      bool forced = false;
       if (pv_[l]) {
         Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
-        sphere_term<MODE>(P, S, cl, pa_[l], pz_[l], pr_[l], pc_[l][0], pc_[l][1], pc_[l][2],
-                          phisum, clr, FM);
+        forced = sphere_term<MODE>(P, S, cl, pa_[l], pz_[l], pr_[l], pc_[l][0], pc_[l][1],
+                                   pc_[l][2], phisum, clr, FM);
       }
-      // a link none of whose samples reached the hinge in this wavefront
-      // has a zero wrench everywhere: its projection would add zeros
-      if (GRAD && __any(pv_[l])) project(tw, l, FM, g);
+      // a link with no force in this wavefront has a zero wrench
+      // everywhere: its projection would add zeros
+      if (GRAD && __any(forced)) project(tw, l, FM, g);
     }
   }
 }
