@@ -49,9 +49,12 @@ __device__ __forceinline__ DS_LDS T* lds(T* p) {
   return (DS_LDS T*)p;
 }
 #ifndef DSOPT_CH
-#define DSOPT_CH 2
+#define DSOPT_CH 4
 #endif
 constexpr int CH = DSOPT_CH;                     // sphere gathers in flight per lane
+// s_waitcnt operand: vector memory count 0, the export and LDS/scalar
+// counts at their maxima (not waited on)
+constexpr int WAIT_VMEM_ALL = 0x0F70;
 
 // Butterfly reductions over a lane group of G = 16, 32 or 64 lanes.  The
 // first four stages pair lanes inside a 16-lane row with DPP (quad
@@ -620,6 +623,12 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
           forced |= sphere_term<MODE>(P, S, cl[k], ra[k], rz[k], rr[k], cxs[k], cys[k], czs[k],
                                       phisum, clr, FM);
       }
+      // every load of the chunk has been consumed: saying so keeps the
+      // next chunk's loads in flight together.  (The loads and their uses
+      // sit in separate wavefront-uniform branches, so without it the
+      // compiler cannot tell which of them are outstanding at the loop's
+      // back edge and drains them all before each sphere's loads.)
+      __builtin_amdgcn_s_waitcnt(WAIT_VMEM_ALL);
     }
     // a link with no force in this wavefront has a zero wrench everywhere:
     // its projection would add zeros
@@ -1029,55 +1038,47 @@ __device__ __forceinline__ void direction(const TileCtx& c, const H& hist, const
   // one seed per wavefront: count and head are wave-uniform
   const int cmax = __builtin_amdgcn_readfirstlane(cnt);
   const int hd = __builtin_amdgcn_readfirstlane(head);
+  // the ring's live slots are read once, all loads in flight together,
+  // and both passes of the recursion run on registers
+  float hs[DS_MAX_HISTORY][NJ], hy[DS_MAX_HISTORY][NJ], hr[DS_MAX_HISTORY];
+  float yy_n = 0.f;
+#pragma unroll
+  for (int k = 0; k < DS_MAX_HISTORY; ++k) {
+    if (k < cmax) {
+      const int slot = ring_slot(hd, k, m);
+#pragma unroll
+      for (int j = 0; j < NJ; ++j) {
+        hs[k][j] = hist.s(slot, j);
+        hy[k][j] = hist.y(slot, j);
+      }
+      hr[k] = hist.rho(slot);
+      if (k == 0) yy_n = hist.yy(slot);
+    }
+  }
   float q[NJ], a[DS_MAX_HISTORY];
 #pragma unroll
   for (int j = 0; j < NJ; ++j) q[j] = g[j];
-  // the slot loads of step k+1 are issued before step k's reduction, so
-  // one memory latency overlaps each dependent dot product
-  float sn[NJ], yn[NJ], rn = 0.f;
-  auto fetch = [&](int k) {
-    const int slot = ring_slot(hd, k, m);
-#pragma unroll
-    for (int j = 0; j < NJ; ++j) {
-      sn[j] = hist.s(slot, j);
-      yn[j] = hist.y(slot, j);
-    }
-    rn = hist.rho(slot);
-  };
-  if (cmax > 0) fetch(0);
 #pragma unroll
   for (int k = 0; k < DS_MAX_HISTORY; ++k) {
     a[k] = 0.f;
     if (k < cmax) {
-      float s[NJ], y[NJ];
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) { s[j] = sn[j]; y[j] = yn[j]; }
-      const float rho = rn;
-      if (k + 1 < cmax) fetch(k + 1);
-      const float ak = rho * grp_sum(dot7(s, q), c.G);
+      const float ak = hr[k] * grp_sum(dot7(hs[k], q), c.G);
       a[k] = ak;
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) q[j] -= ak * y[j];
+      for (int j = 0; j < NJ; ++j) q[j] -= ak * hy[k][j];
     }
   }
-  const int newest = ring_slot(hd, 0, m);
-  float rho_n = hist.rho(newest);
-  float yy_n = hist.yy(newest);
-  float gamma = 1.f / (rho_n * yy_n);   // s^T y / y^T y
+  if (cmax > 0) {
+    const float gamma = 1.f / (hr[0] * yy_n);   // s^T y / y^T y
 #pragma unroll
-  for (int j = 0; j < NJ; ++j) q[j] *= gamma;
-  if (cmax > 0) fetch(cmax - 1);
+    for (int j = 0; j < NJ; ++j) q[j] *= gamma;
+  }
 #pragma unroll
   for (int k = DS_MAX_HISTORY - 1; k >= 0; --k) {
     if (k < cmax) {
-      float s[NJ], y[NJ];
+      const float b = hr[k] * grp_sum(dot7(hy[k], q), c.G);
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) { s[j] = sn[j]; y[j] = yn[j]; }
-      const float rho = rn;
-      if (k > 0) fetch(k - 1);
-      const float b = rho * grp_sum(dot7(y, q), c.G);
-#pragma unroll
-      for (int j = 0; j < NJ; ++j) q[j] += s[j] * (a[k] - b);
+      for (int j = 0; j < NJ; ++j) q[j] += hs[k][j] * (a[k] - b);
     }
   }
   if (cmax > 0) {
