@@ -428,10 +428,13 @@ int ds_plan_create(const ds_robot* robot, const ds_params* prm, void* arena_dev,
   }
   rb.max_per_link = 0;
   for (int l = 0; l < 7; ++l) rb.max_per_link = std::max(rb.max_per_link, rb.link_begin[l + 1] - rb.link_begin[l]);
+  rb.axis_links = 0x7F;
   for (int k = 0; k < rb.ns; ++k) {
     const ds_sphere& sp = robot->spheres[order[k]];
     rb.sph[k] = make_float4(sp.offset[0], sp.offset[1], sp.offset[2], sp.radius);
     rb.perm[k] = order[k];
+    // a link whose spheres all sit on its z axis takes the short centre form
+    if (sp.offset[0] != 0.f || sp.offset[1] != 0.f) rb.axis_links &= ~(1 << (sp.link - 1));
   }
   ParamsDev& P = p->params;
   P.wc = prm->w_collision;

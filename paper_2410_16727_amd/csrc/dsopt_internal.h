@@ -22,6 +22,7 @@ struct RobotDev {
   int32_t ns;
   int32_t max_per_link;              // most spheres on one link
   int32_t link_begin[8];             // spheres of link l (1..7): [link_begin[l-1], link_begin[l])
+  int32_t axis_links;                // bit l-1: every sphere of link l has zero x and y offsets
   float4 sph[DS_MAX_SPHERES];        // offset xyz, radius; sorted by link
   int32_t perm[DS_MAX_SPHERES];      // sorted position -> caller's sphere index
 };

@@ -152,7 +152,7 @@ __device__ __forceinline__ Goal make_goal(const ProbDev& pb) {
 
 struct Sampler {
   __amdgpu_buffer_rsrc_t rsrc;
-  float ox, oy, oz, inv_h, nxm1, nym1, nzm1;
+  float ox, oy, oz, inv_h, h, nxm1, nym1, nzm1;
   float fxm2, fym2, fzm2;          // last cell index per axis, as floats
   int nxm2, nym2, nzm2, cx, cy;    // cells along x and y
   const DS_LDS uint16_t* cm;       // the scene's coarse table (half bits), staged in LDS
@@ -162,7 +162,7 @@ struct Sampler {
 __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
   Sampler s;
   s.rsrc = __builtin_amdgcn_make_buffer_rsrc((void*)sc.rec, (short)0, (int)sc.bytes, RSRC_DWORD3);
-  s.ox = sc.ox; s.oy = sc.oy; s.oz = sc.oz; s.inv_h = sc.inv_h;
+  s.ox = sc.ox; s.oy = sc.oy; s.oz = sc.oz; s.inv_h = sc.inv_h; s.h = 1.f / sc.inv_h;
   s.nxm1 = (float)(sc.nx - 1); s.nym1 = (float)(sc.ny - 1); s.nzm1 = (float)(sc.nz - 1);
   s.nxm2 = sc.nx - 2; s.nym2 = sc.ny - 2; s.nzm2 = sc.nz - 2;
   s.fxm2 = (float)s.nxm2; s.fym2 = (float)s.nym2; s.fzm2 = (float)s.nzm2;
@@ -191,95 +191,107 @@ __device__ __forceinline__ float coarse_at(const Sampler& S, int idx) {
   return (float)__builtin_bit_cast(_Float16, S.cm[idx]);
 }
 
-// Cell lookup for a query point: clamp u = (p - origin) / voxel into the
-// grid, cell min(floor(u), n-2) per axis, fractional position, and which
-// axes were inside (gradient is zero along clamped axes).
-struct Cell {
-  int off;            // byte offset of the cell's 32-byte record
-  int cidx;           // the cell's block in the coarse table
-  float fx, fy, fz;
-  float mx, my, mz;   // 1/voxel inside the grid along the axis, 0 when clamped
+// A sample's place in the grid.  u = (c - origin) / voxel is the sphere
+// centre c in grid units; the sample's cell is trunc(clamp(u, 0, n-2)) per
+// axis (the cell whose corners bracket the clamped point), its fractional
+// position clamp(u, 0, n-1) - cell, and the gradient is zero along axes
+// where u was clamped.
+//
+// A link frame (R, p) maps a sphere offset o to c = p + R o.  For a link
+// whose spheres all lie on its z axis (o = (0, 0, oz)) the link's part is
+// formed once -- u = u0 + oz az with u0 = (p - origin) / voxel and
+// az = R e_z / voxel -- so a sphere costs one FMA per axis.
+struct LinkGrid {
+  float u0[3], az[3];
 };
 
-__device__ __forceinline__ Cell locate(const Sampler& S, float px, float py, float pz) {
-  Cell c;
-  float ux = (px - S.ox) * S.inv_h;
-  float uy = (py - S.oy) * S.inv_h;
-  float uz = (pz - S.oz) * S.inv_h;
-  // clamp into [0, n-1] (one v_med3 each)
-  float cx = __builtin_amdgcn_fmed3f(ux, 0.f, S.nxm1);
-  float cy = __builtin_amdgcn_fmed3f(uy, 0.f, S.nym1);
-  float cz = __builtin_amdgcn_fmed3f(uz, 0.f, S.nzm1);
-  c.mx = (cx == ux) ? S.inv_h : 0.f;
-  c.my = (cy == uy) ? S.inv_h : 0.f;
-  c.mz = (cz == uz) ? S.inv_h : 0.f;
-  ux = cx;
-  uy = cy;
-  uz = cz;
-  int ix = min((int)ux, S.nxm2);
-  int iy = min((int)uy, S.nym2);
-  int iz = min((int)uz, S.nzm2);
-  c.fx = ux - (float)ix;
-  c.fy = uy - (float)iy;
-  c.fz = uz - (float)iz;
-  // record index ix + cx*(iy + cy*iz); every factor fits 24 bits: the
-  // upload keeps (ny-1)(nz-1) below 2^24, and the coarse table has at most
-  // COARSE_MAX blocks (stating the bounds keeps both products 24-bit
-  // multiply-adds)
-  unsigned row = __umul24((unsigned)S.cy, (unsigned)iz) + (unsigned)iy;
-  __builtin_assume(row < (1u << 24));
-  c.off = (int)((__umul24((unsigned)S.cx, row) + (unsigned)ix) << 5);
-  unsigned crow = __umul24((unsigned)S.cdy, (unsigned)(iz >> S.cshift)) + (unsigned)(iy >> S.cshift);
-  __builtin_assume(crow < (1u << 24));
-  c.cidx = (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
-  return c;
+__device__ __forceinline__ LinkGrid link_grid(const Sampler& S, const float* R, const float* p) {
+  LinkGrid g;
+  g.u0[0] = (p[0] - S.ox) * S.inv_h;
+  g.u0[1] = (p[1] - S.oy) * S.inv_h;
+  g.u0[2] = (p[2] - S.oz) * S.inv_h;
+  g.az[0] = R[2] * S.inv_h;
+  g.az[1] = R[5] * S.inv_h;
+  g.az[2] = R[8] * S.inv_h;
+  return g;
 }
 
-// The coarse block of the cell locate() picks for a query point, alone:
-// for u >= 0, min(trunc(min(u, n-1)), n-2) == trunc(min(u, n-2)), so the
-// block index is the same with a third of the arithmetic.
-__device__ __forceinline__ int block_of(const Sampler& S, float px, float py, float pz) {
-  const int ix = (int)__builtin_amdgcn_fmed3f((px - S.ox) * S.inv_h, 0.f, S.fxm2);
-  const int iy = (int)__builtin_amdgcn_fmed3f((py - S.oy) * S.inv_h, 0.f, S.fym2);
-  const int iz = (int)__builtin_amdgcn_fmed3f((pz - S.oz) * S.inv_h, 0.f, S.fzm2);
+// Grid position of the sphere with offset/radius sp on the link (R, p);
+// `axis` (wave-uniform) says the link's spheres sit on its z axis.
+__device__ __forceinline__ void grid_pos(const Sampler& S, const LinkGrid& g, bool axis,
+                                         const float* R, const float* p, float4 sp, float* u) {
+  if (axis) {
+#pragma unroll
+    for (int r = 0; r < 3; ++r) u[r] = fmaf(sp.z, g.az[r], g.u0[r]);
+  } else {
+    const float cx = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
+    const float cy = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
+    const float cz = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
+    u[0] = (cx - S.ox) * S.inv_h;
+    u[1] = (cy - S.oy) * S.inv_h;
+    u[2] = (cz - S.oz) * S.inv_h;
+  }
+}
+
+// The sample's cell: trunc(clamp(u, 0, n-2)) per axis (for u >= 0,
+// min(trunc(min(u, n-1)), n-2) == trunc(min(u, n-2)): one v_med3 and one
+// conversion per axis).
+__device__ __forceinline__ void cell_of(const Sampler& S, const float* u, int* i) {
+  i[0] = (int)__builtin_amdgcn_fmed3f(u[0], 0.f, S.fxm2);
+  i[1] = (int)__builtin_amdgcn_fmed3f(u[1], 0.f, S.fym2);
+  i[2] = (int)__builtin_amdgcn_fmed3f(u[2], 0.f, S.fzm2);
+}
+
+// The cell's block in the coarse table and its record's byte offset.
+// Every product fits 24 bits: the upload keeps (ny-1)(nz-1) below 2^24,
+// and the coarse table has at most COARSE_MAX blocks (stating the bounds
+// keeps both products 24-bit multiply-adds).
+__device__ __forceinline__ int block_index(const Sampler& S, const int* i) {
   const unsigned crow =
-      __umul24((unsigned)S.cdy, (unsigned)(iz >> S.cshift)) + (unsigned)(iy >> S.cshift);
+      __umul24((unsigned)S.cdy, (unsigned)(i[2] >> S.cshift)) + (unsigned)(i[1] >> S.cshift);
   __builtin_assume(crow < (1u << 24));
-  return (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(ix >> S.cshift));
+  return (int)(__umul24((unsigned)S.cdx, crow) + (unsigned)(i[0] >> S.cshift));
 }
 
-// Trilinear blend of a cell record (a: z0 corners, b: z1 corners): the
-// value, and the differences its spatial gradient is formed from.
+__device__ __forceinline__ int record_offset(const Sampler& S, const int* i) {
+  const unsigned row = __umul24((unsigned)S.cy, (unsigned)i[2]) + (unsigned)i[1];
+  __builtin_assume(row < (1u << 24));
+  return (int)((__umul24((unsigned)S.cx, row) + (unsigned)i[0]) << 5);
+}
+
+// Trilinear blend of a cell record (a: z0 corners, b: z1 corners) at the
+// fractional position (fx, fy, fz): the value, and the differences its
+// spatial gradient is formed from.
 struct Blend {
   float d;                          // interpolated distance
   float dx00, dx10, dx01, dx11;     // x differences of the four x edges
   float dy0, dy1, dz;               // y differences at z0/z1, z difference
 };
 
-__device__ __forceinline__ Blend blend_value(const Cell& c, float4 a, float4 b) {
+__device__ __forceinline__ Blend blend_value(float fx, float fy, float fz, float4 a, float4 b) {
   Blend r;
   r.dx00 = a.y - a.x; r.dx10 = a.w - a.z; r.dx01 = b.y - b.x; r.dx11 = b.w - b.z;
-  float c00 = a.x + c.fx * r.dx00;
-  float c10 = a.z + c.fx * r.dx10;
-  float c01 = b.x + c.fx * r.dx01;
-  float c11 = b.z + c.fx * r.dx11;
+  float c00 = a.x + fx * r.dx00;
+  float c10 = a.z + fx * r.dx10;
+  float c01 = b.x + fx * r.dx01;
+  float c11 = b.z + fx * r.dx11;
   r.dy0 = c10 - c00;
   r.dy1 = c11 - c01;
-  float c0 = c00 + c.fy * r.dy0;
-  float c1 = c01 + c.fy * r.dy1;
+  float c0 = c00 + fy * r.dy0;
+  float c1 = c01 + fy * r.dy1;
   r.dz = c1 - c0;
-  r.d = c0 + c.fz * r.dz;
+  r.d = c0 + fz * r.dz;
   return r;
 }
 
-// Its spatial gradient (zero along axes where the point was clamped).
-__device__ __forceinline__ void blend_grad(const Cell& c, const Blend& r, float& gx, float& gy,
-                                           float& gz) {
-  float e0 = r.dx00 + c.fy * (r.dx10 - r.dx00);
-  float e1 = r.dx01 + c.fy * (r.dx11 - r.dx01);
-  gx = (e0 + c.fz * (e1 - e0)) * c.mx;
-  gy = (r.dy0 + c.fz * (r.dy1 - r.dy0)) * c.my;
-  gz = r.dz * c.mz;
+// Its spatial gradient in grid units (times 1/voxel by the caller).
+__device__ __forceinline__ void blend_grad(float fy, float fz, const Blend& r, float& gx,
+                                           float& gy, float& gz) {
+  float e0 = r.dx00 + fy * (r.dx10 - r.dx00);
+  float e1 = r.dx01 + fy * (r.dx11 - r.dx01);
+  gx = e0 + fz * (e1 - e0);
+  gy = r.dy0 + fz * (r.dy1 - r.dy0);
+  gz = r.dz;
 }
 
 __device__ __forceinline__ float4 load_rec(const Sampler& S, int off) {
@@ -373,15 +385,20 @@ struct Team {
   }
 };
 
-// Hinge cost of one sphere sample and, with GRAD, its force accumulated into
-// the link wrench (F, M about the world origin).  Returns whether the force
-// terms ran (some lane of the wavefront inside the hinge band).
+// Hinge cost of one sphere sample (grid position u, cell ci, cell record
+// ra/rz, radius r) and, with GRAD, its force accumulated into the link
+// wrench (F, M about the world origin).  Returns whether the force terms
+// ran (some lane of the wavefront inside the hinge band).
 template <int MODE>
-__device__ __forceinline__ bool sphere_term(const ParamsDev& P, const Sampler& S, const Cell& cl,
-                                            float4 ra, float4 rz, float r, float cx, float cy,
-                                            float cz, float& phisum, float& clr, float* FM) {
+__device__ __forceinline__ bool sphere_term(const ParamsDev& P, const Sampler& S, const float* u,
+                                            const int* ci, float4 ra, float4 rz, float r,
+                                            float& phisum, float& clr, float* FM) {
   constexpr bool GRAD = (MODE == EV_GRAD);
-  const Blend bl = blend_value(cl, ra, rz);
+  const float cx = __builtin_amdgcn_fmed3f(u[0], 0.f, S.nxm1);
+  const float cy = __builtin_amdgcn_fmed3f(u[1], 0.f, S.nym1);
+  const float cz = __builtin_amdgcn_fmed3f(u[2], 0.f, S.nzm1);
+  const float fy = cy - (float)ci[1], fz = cz - (float)ci[2];
+  const Blend bl = blend_value(cx - (float)ci[0], fy, fz, ra, rz);
   float D = bl.d - r;
   float De = D - P.eps;
   float phi = (D < P.eps) ? De * De * P.half_inv_eps : 0.f;
@@ -394,15 +411,23 @@ __device__ __forceinline__ bool sphere_term(const ParamsDev& P, const Sampler& S
   const bool band = GRAD && __any(D < P.eps);
   if (band) {
     float gx, gy, gz;
-    blend_grad(cl, bl, gx, gy, gz);
+    blend_grad(fy, fz, bl, gx, gy, gz);
+    // world units; zero along axes where the point was clamped
+    gx *= (cx == u[0]) ? S.inv_h : 0.f;
+    gy *= (cy == u[1]) ? S.inv_h : 0.f;
+    gz *= (cz == u[2]) ? S.inv_h : 0.f;
     float dphi = (D < P.eps) ? De * P.inv_eps : 0.f;
     dphi = (D < 0.f) ? -1.f : dphi;
     float w = P.wc * dphi;
-    float fx = w * gx, fy = w * gy, fz = w * gz;
-    FM[0] += fx; FM[1] += fy; FM[2] += fz;
-    FM[3] += cy * fz - cz * fy;
-    FM[4] += cz * fx - cx * fz;
-    FM[5] += cx * fy - cy * fx;
+    float fx = w * gx, fyy = w * gy, fzz = w * gz;
+    // the sphere centre (the moment arm) back from its grid position
+    const float px = fmaf(u[0], S.h, S.ox);
+    const float py = fmaf(u[1], S.h, S.oy);
+    const float pz = fmaf(u[2], S.h, S.oz);
+    FM[0] += fx; FM[1] += fyy; FM[2] += fzz;
+    FM[3] += py * fzz - pz * fyy;
+    FM[4] += pz * fx - px * fzz;
+    FM[5] += px * fyy - py * fx;
   }
   return band;
 }
@@ -542,9 +567,10 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
   R[0] = 1.f; R[1] = 0.f; R[2] = 0.f; R[3] = 0.f; R[4] = 1.f; R[5] = 0.f;
   R[6] = 0.f; R[7] = 0.f; R[8] = 1.f;
   p[0] = p[1] = p[2] = 0.f;
-  // PIPE: the lane's sample of every link
+  // PIPE: the lane's sample of every link (grid position, radius, coarse
+  // minimum, record)
   float4 pa_[PIPE ? NJ : 1], pz_[PIPE ? NJ : 1];
-  float pc_[PIPE ? NJ : 1][3], pr_[PIPE ? NJ : 1], pcm_[PIPE ? NJ : 1];
+  float pu_[PIPE ? NJ : 1][3], pr_[PIPE ? NJ : 1], pcm_[PIPE ? NJ : 1];
   bool pv_[PIPE ? NJ : 1];
 #pragma unroll
   for (int l = 0; l < NJ; ++l) {
@@ -569,18 +595,22 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
     }
     if (GRAD) tw.put(l, R, p);
     const int s0 = rb->link_begin[l], s1 = rb->link_begin[l + 1];
+    const bool axis = (rb->axis_links >> l) & 1;   // wave-uniform
+    const LinkGrid lg = link_grid(S, R, p);
     if (PIPE) {
       const int sk = s0 + cp;
       pv_[l] = active && sk < s1;   // lanes past the horizon gather nothing
       if (pv_[l]) {
-        float4 sp = s_sph[sk];
-        pc_[l][0] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
-        pc_[l][1] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
-        pc_[l][2] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
+        const float4 sp = s_sph[sk];
+        grid_pos(S, lg, axis, R, p, sp, pu_[l]);
         pr_[l] = sp.w;
         // the coarse minimum is read here and tested after the chain, so
         // no link waits for its lookup before the next frame
-        if (SKIP) pcm_[l] = coarse_at(S, block_of(S, pc_[l][0], pc_[l][1], pc_[l][2]));
+        if (SKIP) {
+          int ci[3];
+          cell_of(S, pu_[l], ci);
+          pcm_[l] = coarse_at(S, block_index(S, ci));
+        }
       }
       continue;
     }
@@ -593,26 +623,25 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
     // zero hinge (a trilinear blend stays within its corners' range): it
     // loads nothing.
     for (int s = s0; s < s1; s += LW * CH) {
-      Cell cl[CH];
+      float u[CH][3], rr[CH];
+      int ci[CH][3];
       float4 ra[CH], rz[CH];
-      float cxs[CH], cys[CH], czs[CH], rr[CH];
       bool use[CH];
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         const int sk = s + k * LW + cp;
         use[k] = active && sk < s1;
         if (use[k]) {
-          float4 sp = s_sph[sk];
-          cxs[k] = R[0] * sp.x + R[1] * sp.y + R[2] * sp.z + p[0];
-          cys[k] = R[3] * sp.x + R[4] * sp.y + R[5] * sp.z + p[1];
-          czs[k] = R[6] * sp.x + R[7] * sp.y + R[8] * sp.z + p[2];
+          const float4 sp = s_sph[sk];
+          grid_pos(S, lg, axis, R, p, sp, u[k]);
+          cell_of(S, u[k], ci[k]);
           rr[k] = sp.w;
-          cl[k] = locate(S, cxs[k], cys[k], czs[k]);
-          if (SKIP && coarse_at(S, cl[k].cidx) >= sp.w + P.far) {
+          if (SKIP && coarse_at(S, block_index(S, ci[k])) >= sp.w + P.far) {
             use[k] = false;   // zero hinge, zero gradient
           } else {
-            ra[k] = load_rec(S, cl[k].off);
-            rz[k] = load_rec(S, cl[k].off + 16);
+            const int off = record_offset(S, ci[k]);
+            ra[k] = load_rec(S, off);
+            rz[k] = load_rec(S, off + 16);
             ++ng;
           }
         }
@@ -620,8 +649,7 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
 #pragma unroll
       for (int k = 0; k < CH; ++k) {
         if (use[k])
-          forced |= sphere_term<MODE>(P, S, cl[k], ra[k], rz[k], rr[k], cxs[k], cys[k], czs[k],
-                                      phisum, clr, FM);
+          forced |= sphere_term<MODE>(P, S, u[k], ci[k], ra[k], rz[k], rr[k], phisum, clr, FM);
       }
       // every load of the chunk has been consumed: saying so keeps the
       // next chunk's loads in flight together.  (The loads and their uses
@@ -642,9 +670,11 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
         if (SKIP && pcm_[l] >= pr_[l] + P.far) {
           pv_[l] = false;   // zero hinge, zero gradient: nothing to add
         } else {
-          const Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
-          pa_[l] = load_rec(S, cl.off);
-          pz_[l] = load_rec(S, cl.off + 16);
+          int ci[3];
+          cell_of(S, pu_[l], ci);
+          const int off = record_offset(S, ci);
+          pa_[l] = load_rec(S, off);
+          pz_[l] = load_rec(S, off + 16);
           ++ng;
         }
       }
@@ -654,9 +684,9 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
       float FM[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
       bool forced = false;
       if (pv_[l]) {
-        Cell cl = locate(S, pc_[l][0], pc_[l][1], pc_[l][2]);
-        forced = sphere_term<MODE>(P, S, cl, pa_[l], pz_[l], pr_[l], pc_[l][0], pc_[l][1],
-                                   pc_[l][2], phisum, clr, FM);
+        int ci[3];
+        cell_of(S, pu_[l], ci);
+        forced = sphere_term<MODE>(P, S, pu_[l], ci, pa_[l], pz_[l], pr_[l], phisum, clr, FM);
       }
       // a link with no force in this wavefront has a zero wrench
       // everywhere: its projection would add zeros
