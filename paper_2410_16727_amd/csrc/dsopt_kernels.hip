@@ -89,27 +89,32 @@ __device__ __forceinline__ float from_prev(float v) {
       __builtin_amdgcn_update_dpp(0, __float_as_int(v), DPP_WAVE_SHR1, 0xF, 0xF, true));
 }
 
-// The value of lane ^ 16 (v_permlane16_swap exchanges the odd rows of its
-// first operand with the even rows of its second: with both operands v, an
-// even row finds its partner row in the second result, an odd row in the
-// first) and of lane ^ 32 (v_permlane32_swap: the upper half of the first
-// operand with the lower half of the second).
-__device__ __forceinline__ unsigned xor16_bits(unsigned v) {
-  const auto r = __builtin_amdgcn_permlane16_swap(v, v, true, false);
-  return (threadIdx.x & 16) ? r[0] : r[1];
-}
-__device__ __forceinline__ unsigned xor32_bits(unsigned v) {
-  const auto r = __builtin_amdgcn_permlane32_swap(v, v, true, false);
-  return (threadIdx.x & 32) ? r[0] : r[1];
-}
-__device__ __forceinline__ float lane_xor(float v, int off) {
-  return __uint_as_float(off == 16 ? xor16_bits(__float_as_uint(v))
-                                   : xor32_bits(__float_as_uint(v)));
-}
-
 struct OpSum { __device__ static float f(float a, float b) { return a + b; } };
 struct OpMax { __device__ static float f(float a, float b) { return fmaxf(a, b); } };
 struct OpMin { __device__ static float f(float a, float b) { return fminf(a, b); } };
+
+// v combined with lane ^ 16's v (v_permlane16_swap with v as both operands
+// exchanges the odd rows of the first with the even rows of the second: in
+// every lane one result is its own value and the other its partner's) and
+// with lane ^ 32's (v_permlane32_swap: the upper half of the first operand
+// with the lower half of the second).  The operations are commutative, so
+// combining the two results needs no per-lane select.
+template <class Op>
+__device__ __forceinline__ float xor16_reduce(float v) {
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(v), __float_as_uint(v), true,
+                                                  false);
+  return Op::f(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+template <class Op>
+__device__ __forceinline__ float xor32_reduce(float v) {
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(v), __float_as_uint(v), true,
+                                                  false);
+  return Op::f(__uint_as_float(r[0]), __uint_as_float(r[1]));
+}
+template <class Op>
+__device__ __forceinline__ float xor_reduce(float v, int off) {
+  return off == 16 ? xor16_reduce<Op>(v) : xor32_reduce<Op>(v);
+}
 
 template <class Op>
 __device__ __forceinline__ float grp_reduce(float v, int G) {
@@ -117,8 +122,8 @@ __device__ __forceinline__ float grp_reduce(float v, int G) {
   v = Op::f(v, dpp<DPP_QUAD_XOR2>(v));
   v = Op::f(v, dpp<DPP_HALF_MIRROR>(v));
   v = Op::f(v, dpp<DPP_MIRROR>(v));
-  if (G > 16) v = Op::f(v, lane_xor(v, 16));
-  if (G > 32) v = Op::f(v, lane_xor(v, 32));
+  if (G > 16) v = xor16_reduce<Op>(v);
+  if (G > 32) v = xor32_reduce<Op>(v);
   return v;
 }
 
@@ -861,11 +866,11 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   // ends with the same value)
   if (!scatter)
   for (int off = G; off < WAVE; off <<= 1) {
-    phisum += lane_xor(phisum, off);
-    if (MODE == EV_RESULT) clr = fminf(clr, lane_xor(clr, off));
+    phisum = xor_reduce<OpSum>(phisum, off);
+    if (MODE == EV_RESULT) clr = xor_reduce<OpMin>(clr, off);
     if (GRAD) {
 #pragma unroll
-      for (int j = 0; j < NJ; ++j) o.g[j] += lane_xor(o.g[j], off);
+      for (int j = 0; j < NJ; ++j) o.g[j] = xor_reduce<OpSum>(o.g[j], off);
     }
   }
   if (scatter) {
@@ -883,7 +888,7 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
     for (int cc = tm.w; cc < NC; cc += tm.W) {
       float v = base[cc * WAVE];
       for (int u = 1; u < tm.W; ++u) v += base[(u * PART + cc) * WAVE];
-      for (int off = G; off < WAVE; off <<= 1) v += lane_xor(v, off);
+      for (int off = G; off < WAVE; off <<= 1) v = xor_reduce<OpSum>(v, off);
       base[cc * WAVE] = v;
     }
     tm.sync();
