@@ -525,7 +525,7 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
     if ((long long)cdx * cdy * cdz <= COARSE_MAX) break;
   }
   const size_t coarse_at = (rec_bytes + 255) / 256 * 256;
-  size_t off = arena_alloc(p, coarse_at + COARSE_MAX * sizeof(uint16_t));
+  size_t off = arena_alloc(p, coarse_at + COARSE_BYTES);
   if (off == SIZE_MAX) return fail(DS_ERR_NOMEM, "arena full (scene %d, %zu B)", scene_id, rec_bytes);
   const float* src = vals;
   size_t tmp_off = SIZE_MAX;
@@ -545,8 +545,13 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
     src = reinterpret_cast<const float*>(p->arena.ptr(tmp_off));
   }
   HIP_TRY(launch_esdf_pack(src, nx, ny, nz, reinterpret_cast<float4*>(p->arena.ptr(off)), s));
-  uint16_t* coarse = reinterpret_cast<uint16_t*>(p->arena.ptr(off) + coarse_at);
-  HIP_TRY(launch_coarse(src, nx, ny, nz, cshift, cdx, cdy, cdz, coarse, s));
+  uint8_t* coarse = p->arena.ptr(off) + coarse_at;
+  // one level of the coarse table: the largest sphere's skip distance
+  // (radius + far) spans 8 levels, so every sphere's test fits in 15
+  float rmax = 0.f;
+  for (int k = 0; k < p->robot.ns; ++k) rmax = std::max(rmax, p->robot.sph[k].w);
+  const float cq = (rmax + p->params.far) / 8.f;
+  HIP_TRY(launch_coarse(src, nx, ny, nz, cshift, cdx, cdy, cdz, cq, coarse, s));
   if (tmp_off != SIZE_MAX)
     if (int rc = defer_free(p, tmp_off, s)) return rc;
   SceneRec rec;
@@ -557,6 +562,7 @@ int ds_esdf_upload(ds_plan* p, int32_t scene_id, const float* vals, int nx, int 
   rec.dev.inv_h = 1.f / voxel;
   rec.dev.bytes = (uint32_t)rec_bytes;
   rec.dev.coarse = coarse;
+  rec.dev.cq = cq;
   rec.dev.cshift = cshift;
   rec.dev.cdx = cdx; rec.dev.cdy = cdy; rec.dev.cdz = cdz;
   p->scenes[scene_id] = rec;

@@ -42,19 +42,21 @@ struct ParamsDev {
 
 // One resident scene: the 8 corners of cell (i,j,k) are the 32-byte record
 // i + (nx-1)*(j + (ny-1)*k): [c000 c100 c010 c110 | c001 c101 c011 c111].
-// Coarse table: the minimum node distance over each block of 2^cshift
-// cells per axis (node range of the block's cells, inclusive), at most
-// COARSE_MAX blocks, x fastest, as IEEE half-precision values rounded
-// towards minus infinity (a lower bound of the float minimum: 8 KB).
-constexpr int COARSE_MAX = 4096;
-constexpr int COARSE_FLOATS = COARSE_MAX / 2;   // the table's size in 4-byte words
-
+// Coarse table: for each block of 2^cshift cells per axis (x fastest, at
+// most COARSE_MAX blocks), a 4-bit level L bounding the minimum node
+// distance m over the block's nodes from below: the largest L <= 15 with
+// L * cq <= m in float arithmetic (0 when m is negative or NaN); two blocks
+// per byte, the even block in the low nibble (16 KB).
+constexpr int COARSE_MAX = 32768;
+constexpr int COARSE_BYTES = COARSE_MAX / 2;
+constexpr int COARSE_FLOATS = COARSE_BYTES / 4;   // the table's size in 4-byte words
 struct SceneDev {
   const float4* rec;
   int32_t nx, ny, nz;    // node counts
   float ox, oy, oz, inv_h;
   uint32_t bytes;        // size of the record array
-  const uint16_t* coarse;   // [cdz][cdy][cdx] block minima (half bits, rounded down)
+  const uint8_t* coarse;    // [cdz][cdy][cdx] block levels (4 bits each)
+  float cq;                 // distance of one level
   int32_t cshift, cdx, cdy, cdz;
 };
 
@@ -123,8 +125,9 @@ namespace dsk {
 inline bool params_ext(const ParamsDev& P) { return P.ws != 0.f || P.nsub > 0; }
 hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* rec,
                             hipStream_t s);
+// The coarse table of a scene into out (COARSE_BYTES, cleared here).
 hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
-                         int cdz, uint16_t* out, hipStream_t s);
+                         int cdz, float cq, uint8_t* out, hipStream_t s);
 // counter: N_XCD ints when xcd_ranges (N_XCD + 1 ints: the per-XCD queues'
 // bounds in the tile table) is given, else one.
 // tile_list (optional): the queue order, a permutation of 0..n_tiles-1.

@@ -160,7 +160,8 @@ struct Sampler {
   float ox, oy, oz, inv_h, h, nxm1, nym1, nzm1;
   float fxm2, fym2, fzm2;          // last cell index per axis, as floats
   int nxm2, nym2, nzm2, cx, cy;    // cells along x and y
-  const DS_LDS uint16_t* cm;       // the scene's coarse table (half bits), staged in LDS
+  const DS_LDS uint8_t* cm;        // the scene's coarse table (4-bit levels), staged in LDS
+  float cq;                        // distance of one level
   int cshift, cdx, cdy;
 };
 
@@ -174,6 +175,7 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
   s.cx = sc.nx - 1;
   s.cy = sc.ny - 1;
   s.cm = nullptr;
+  s.cq = sc.cq;
   s.cshift = sc.cshift;
   s.cdx = sc.cdx;
   s.cdy = sc.cdy;
@@ -181,19 +183,21 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
 }
 
 // Copy the scene's coarse table into LDS (threads tid = 0..nth-1 of the
-// group that shares it; the caller synchronises them afterwards), two
-// entries per 4-byte word.
-__device__ __forceinline__ void stage_coarse(const SceneDev& sc, DS_LDS uint16_t* dst, int tid,
+// group that shares it; the caller synchronises them afterwards), eight
+// levels per 4-byte word.
+__device__ __forceinline__ void stage_coarse(const SceneDev& sc, DS_LDS uint8_t* dst, int tid,
                                              int nth) {
-  const int n = (sc.cdx * sc.cdy * sc.cdz + 1) / 2;
+  const int n = (sc.cdx * sc.cdy * sc.cdz + 7) / 8;
   const DS_GLOBAL uint32_t* src = glb(reinterpret_cast<const uint32_t*>(sc.coarse));
   DS_LDS uint32_t* d32 = (DS_LDS uint32_t*)dst;
   for (int i = tid; i < n; i += nth) d32[i] = src[i];
 }
 
-// A coarse-table entry as a float.
+// A coarse-table entry as a distance: level * cq, at most the block's
+// minimum node distance.
 __device__ __forceinline__ float coarse_at(const Sampler& S, int idx) {
-  return (float)__builtin_bit_cast(_Float16, S.cm[idx]);
+  const unsigned b = S.cm[idx >> 1];
+  return (float)((b >> ((idx & 1) << 2)) & 15u) * S.cq;
 }
 
 // A sample's place in the grid.  u = (c - origin) / voxel is the sphere
@@ -1386,7 +1390,7 @@ enum { PH_INIT = 0, PH_DIR = 1, PH_TRIAL = 2, PH_ACCEPT = 3 };
 template <bool LDS_HIST, bool EXT>
 __device__ __forceinline__ void run_tile(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
                          const ProbDev* __restrict__ probs, const TileDev& td, int max_iters,
-                         Team& tm, float* hist_lds, uint16_t* coarse_lds, float* dir_lds) {
+                         Team& tm, float* hist_lds, uint8_t* coarse_lds, float* dir_lds) {
   TileCtx c;
   c.rb = rb;
   c.P = *pp;
@@ -1673,14 +1677,14 @@ k_optimize(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
     TileDev td = tiles[ti];
     if constexpr (TEAM) {
       run_tile<true, EXT>(rb, pp, probs, td, max_iters, tm, s_dyn + 2 * tm.W * PART * WAVE,
-                          reinterpret_cast<uint16_t*>(s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS),
+                          reinterpret_cast<uint8_t*>(s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS),
                           s_dyn + 2 * tm.W * PART * WAVE + H_FLOATS + COARSE_FLOATS);
       __syncthreads();   // the LDS ring is free for the next tile
     } else {
       // this wavefront's coarse table (uniform)
       const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / WAVE));
       run_tile<false, EXT>(rb, pp, probs, td, max_iters, tm, nullptr,
-                           reinterpret_cast<uint16_t*>(s_dyn + wv * COARSE_FLOATS), nullptr);
+                           reinterpret_cast<uint8_t*>(s_dyn + wv * COARSE_FLOATS), nullptr);
     }
   }
 }
@@ -1828,7 +1832,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
        int with_grad, int W) {
   extern __shared__ float s_team[];
-  __shared__ uint16_t s_cm[COARSE_MAX];
+  __shared__ uint8_t s_cm[COARSE_BYTES];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
@@ -1869,7 +1873,7 @@ k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
         int n_steps, float* __restrict__ J_out, int W) {
   extern __shared__ float s_team[];
-  __shared__ uint16_t s_cm[COARSE_MAX];
+  __shared__ uint8_t s_cm[COARSE_BYTES];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
@@ -1956,15 +1960,17 @@ __global__ void k_esdf_pack(const float* __restrict__ v, int nx, int ny, int nz,
   }
 }
 
-// Coarse table: minimum node value over each block of 2^shift cells per axis
-// (the nodes of the block's cells, inclusive of the far faces).  One
-// workgroup per block: its threads stride over the block's nodes (x runs
-// contiguous), then a shuffle and LDS minimum.
+// Coarse table: minimum node value m over each block of 2^shift cells per
+// axis (the nodes of the block's cells, inclusive of the far faces), kept
+// as the 4-bit level L = the largest L <= 15 with L * cq <= m (0 for a
+// negative or NaN m).  One workgroup per block: its threads stride over
+// the block's nodes (x runs contiguous), then a shuffle and LDS minimum;
+// the level lands in its nibble of the cleared table with an atomic or.
 constexpr int COARSE_THREADS = 256;
 
 __global__ void __launch_bounds__(COARSE_THREADS)
 k_coarse(const float* __restrict__ v, int nx, int ny, int nz, int shift, int cdx, int cdy,
-         uint16_t* __restrict__ out) {
+         float cq, unsigned* __restrict__ out) {
   __shared__ float s_min[COARSE_THREADS / WAVE];
   const int b = blockIdx.x;
   const int bx = b % cdx, by = (b / cdx) % cdy, bz = b / (cdx * cdy);
@@ -1984,17 +1990,14 @@ k_coarse(const float* __restrict__ v, int nx, int ny, int nz, int shift, int cdx
   if (threadIdx.x == 0) {
     float r = s_min[0];
     for (int w = 1; w < COARSE_THREADS / WAVE; ++w) r = fminf(r, s_min[w]);
-    // half precision rounded towards minus infinity: the nearest half,
-    // stepped down one unit when it lies above r (overflow to +inf steps
-    // to the largest finite half; NaN stays NaN and never proves a skip)
-    _Float16 hv = (_Float16)r;
-    uint16_t bits = __builtin_bit_cast(uint16_t, hv);
-    if ((float)hv > r) {
-      if (bits == 0x0000u) bits = 0x8001u;
-      else if (bits & 0x8000u) bits = (uint16_t)(bits + 1u);
-      else bits = (uint16_t)(bits - 1u);
+    // fminf drops NaN node values; a NaN minimum (every node NaN) or a
+    // negative one gives level 0, which never proves a skip
+    unsigned L = 0;
+    if (r >= 0.f) {
+      L = (unsigned)fminf(floorf(r / cq), 15.f);
+      while (L > 0 && (float)L * cq > r) --L;   // the quotient may have rounded up
     }
-    out[b] = bits;
+    atomicOr(&out[b >> 3], L << ((b & 7) * 4));
   }
 }
 
@@ -2078,10 +2081,11 @@ hipError_t launch_esdf_pack(const float* vals, int nx, int ny, int nz, float4* r
 }
 
 hipError_t launch_coarse(const float* vals, int nx, int ny, int nz, int shift, int cdx, int cdy,
-                         int cdz, uint16_t* out, hipStream_t s) {
-  (void)cdz;
+                         int cdz, float cq, uint8_t* out, hipStream_t s) {
+  hipError_t e = launch_zero_i32(reinterpret_cast<int*>(out), COARSE_BYTES / 4, s);
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_coarse, dim3(cdx * cdy * cdz), dim3(COARSE_THREADS), 0, s, vals, nx, ny,
-                     nz, shift, cdx, cdy, out);
+                     nz, shift, cdx, cdy, cq, reinterpret_cast<unsigned*>(out));
   return hipGetLastError();
 }
 
