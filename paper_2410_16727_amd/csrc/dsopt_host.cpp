@@ -266,17 +266,20 @@ int run_optimize(ds_plan* p, const ds_problem* probs, int n, hipStream_t s, floa
     }
   }
   // Batched launches: one tile queue per XCD.  Problems go to the XCD with
-  // the least work so far, largest first (work ~ S T), so each problem's
-  // tiles -- and the records of its scene -- stay in one XCD's L2; inside a
-  // queue the longest tiles come first (a tile's time grows with its group
-  // size, and the short ones then fill the tail).  Per-seed arithmetic does
-  // not depend on the order.
+  // the least work so far, largest first, so each problem's tiles -- and
+  // the records of its scene -- stay in one XCD's L2; inside a queue the
+  // longest tiles come first (a tile's time grows with its group size, and
+  // the short ones then fill the tail).  A problem's work is counted as
+  // S G: a seed runs at wavefront width whatever its horizon inside the
+  // lane group, and counting the long, most variable 64-lane seeds at more
+  // than their mean time spreads them over the XCDs.  Per-seed arithmetic
+  // does not depend on the order.
   std::vector<int> xcd_ranges;
   if (n > 1) {
     constexpr int NX = N_XCD;
     std::vector<int> order(n), owner(n);
     for (int i = 0; i < n; ++i) order[i] = i;
-    auto work = [&](int i) { return (long long)probs[i].n_seeds * probs[i].horizon; };
+    auto work = [&](int i) { return (long long)probs[i].n_seeds * pd[i].G; };
     std::stable_sort(order.begin(), order.end(), [&](int a, int b) { return work(a) > work(b); });
     long long load[NX] = {0};
     for (int i : order) {
