@@ -1781,13 +1781,35 @@ __global__ void __launch_bounds__(ORDER_THREADS) k_queue_order(const TileDev* __
   __syncthreads();
   for (int i = b + threadIdx.x; i < e; i += blockDim.x) atomicAdd(&bins[order_key(tiles[i])], 1);
   __syncthreads();
-  if (threadIdx.x == 0) {   // start of each key's run, largest key first
-    int run = 0;
-    for (int k = ORDER_BINS - 1; k >= 0; --k) {
-      const int c = bins[k];
-      bins[k] = run;
-      run += c;
-    }
+  // start of each key's run, largest key first: an exclusive scan of the
+  // bins in descending key order.  Thread t owns the PER keys from
+  // ORDER_BINS - 1 - PER t downwards; the threads' totals are scanned per
+  // wavefront (shuffles), then across the wavefronts (LDS).
+  constexpr int PER = ORDER_BINS / ORDER_THREADS;
+  constexpr int NW = ORDER_THREADS / WAVE;
+  __shared__ int wsum[NW];
+  const int t = threadIdx.x, lane = t & (WAVE - 1), wv = t / WAVE;
+  int cnt[PER], tot = 0;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    cnt[q] = bins[ORDER_BINS - 1 - (PER * t + q)];
+    tot += cnt[q];
+  }
+  int inc = tot;   // inclusive scan of the totals inside the wavefront
+#pragma unroll
+  for (int off = 1; off < WAVE; off <<= 1) {
+    const int o = __shfl_up(inc, off);
+    if (lane >= off) inc += o;
+  }
+  if (lane == WAVE - 1) wsum[wv] = inc;
+  __syncthreads();
+  int base = 0;
+  for (int w = 0; w < wv; ++w) base += wsum[w];
+  int run = base + inc - tot;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    bins[ORDER_BINS - 1 - (PER * t + q)] = run;
+    run += cnt[q];
   }
   __syncthreads();
   for (int i = b + threadIdx.x; i < e; i += blockDim.x)
