@@ -183,14 +183,35 @@ __device__ __forceinline__ Sampler make_sampler(const SceneDev& sc) {
 }
 
 // Copy the scene's coarse table into LDS (threads tid = 0..nth-1 of the
-// group that shares it; the caller synchronises them afterwards), eight
-// levels per 4-byte word.
+// group that shares it; the caller synchronises them afterwards) in
+// 16-byte pieces, STAGE_UNROLL loads in flight per thread before their LDS
+// stores (one load at a time made every piece a memory round trip).  The
+// table's allocation and both ends are 16-byte aligned.
+constexpr int STAGE_UNROLL = 4;
 __device__ __forceinline__ void stage_coarse(const SceneDev& sc, DS_LDS uint8_t* dst, int tid,
                                              int nth) {
-  const int n = (sc.cdx * sc.cdy * sc.cdz + 7) / 8;
+  const int n = (sc.cdx * sc.cdy * sc.cdz + 31) / 32;   // 32 levels per piece
   const DS_GLOBAL uint32_t* src = glb(reinterpret_cast<const uint32_t*>(sc.coarse));
-  DS_LDS uint32_t* d32 = (DS_LDS uint32_t*)dst;
-  for (int i = tid; i < n; i += nth) d32[i] = src[i];
+  DS_LDS uint32_t* d = (DS_LDS uint32_t*)dst;
+  for (int i0 = tid; i0 < n; i0 += STAGE_UNROLL * nth) {
+    uint32_t v[STAGE_UNROLL][4];
+#pragma unroll
+    for (int u = 0; u < STAGE_UNROLL; ++u) {
+      const int i = i0 + u * nth;
+      if (i < n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) v[u][q] = src[4 * i + q];
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < STAGE_UNROLL; ++u) {
+      const int i = i0 + u * nth;
+      if (i < n) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) d[4 * i + q] = v[u][q];
+      }
+    }
+  }
 }
 
 // A coarse-table entry as a distance: level * cq, at most the block's
@@ -1854,7 +1875,7 @@ k_cost(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
        const float* __restrict__ dJ, float* __restrict__ J_out, float* __restrict__ dX,
        int with_grad, int W) {
   extern __shared__ float s_team[];
-  __shared__ uint8_t s_cm[COARSE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t s_cm[COARSE_BYTES];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
@@ -1895,7 +1916,7 @@ k_guide(const RobotDev* __restrict__ rb, const ParamsDev* __restrict__ pp,
         const ProbDev* __restrict__ pb, float* __restrict__ X, int S, int T, int G, float alpha,
         int n_steps, float* __restrict__ J_out, int W) {
   extern __shared__ float s_team[];
-  __shared__ uint8_t s_cm[COARSE_BYTES];
+  __shared__ __attribute__((aligned(16))) uint8_t s_cm[COARSE_BYTES];
   if (pp->skip) stage_coarse(pb->sc, lds(s_cm), threadIdx.x, blockDim.x);
   stage_spheres(rb);
   const int lane = threadIdx.x & (WAVE - 1);
