@@ -628,7 +628,13 @@ __device__ __forceinline__ void sweep(const RobotDev* __restrict__ rb, const Par
     const bool axis = (rb->axis_links >> l) & 1;   // wave-uniform
     const LinkGrid lg = link_grid(S, R, p);
     if (PIPE) {
-      const int sk = s0 + cp;
+      // copy cp takes sphere (cp - rot) mod LW of the link, rot advancing by
+      // the longest link's sphere count from link to link: when there are
+      // more copies than spheres, consecutive links land on different
+      // copies and the samples spread evenly over the wavefronts
+      int idx = cp - (l * rb->max_per_link) % LW;
+      if (idx < 0) idx += LW;
+      const int sk = s0 + idx;
       pv_[l] = active && sk < s1;   // lanes past the horizon gather nothing
       if (pv_[l]) {
         const float4 sp = s_sph[sk];
