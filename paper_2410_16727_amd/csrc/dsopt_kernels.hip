@@ -805,12 +805,14 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
   // goal pose, joint limits and smoothness: the same for every copy of the
   // waypoint, so one wavefront of the team computes each and only its first
   // copy adds them to its share before the sums below -- the goal on the
-  // second wavefront, limits and smoothness on the third (off the first
-  // one's path), except in the result pass, whose goal errors the first
+  // second wavefront, the limits on the third and the smoothness on the
+  // fourth (off the first one's path; smaller teams fold them onto fewer
+  // wavefronts), except in the result pass, whose goal errors the first
   // one writes
   const int xg = (MODE == EV_RESULT || tm.W == 1) ? 0 : 1;
   const int xl = (MODE == EV_RESULT || tm.W < 3) ? xg : 2;
-  if (tm.w == xg || tm.w == xl) {
+  const int xs = (MODE == EV_RESULT || tm.W < 4) ? xl : 3;
+  if (tm.w == xg || tm.w == xl || tm.w == xs) {
     const bool first = lane < G;
     const bool last = (t == T - 1);
     float ge[NJ];
@@ -881,9 +883,9 @@ __device__ __forceinline__ EvalOut evaluate(const RobotDev* __restrict__ rb,
       lim += hp * hp + lp * lp;
       if (GRAD) ge[j] += 2.f * P.wl * (hp - lp);
     }
-    float sm = smoothness<GRAD>(P, q, t, T, ge);
-    extra_l = P.wl * lim + sm;
+    extra_l = P.wl * lim;
     }
+    if (tm.w == xs) extra_l += smoothness<GRAD>(P, q, t, T, ge);
     coll += first ? extra_l + extra_g : 0.f;
     if (GRAD) {
 #pragma unroll
