@@ -155,18 +155,18 @@ def test_full_batch_equals_plain(batchD):
         plan.release(900 + i)
 
 
-def test_batches_on_two_streams_equal_one_at_a_time(batchD):
-    """Two full batches in flight at once on two streams (the second
-    enqueued while the first runs, as a pipelined caller does): every
+def test_batches_on_three_streams_equal_one_at_a_time(batchD):
+    """Three full batches in flight at once on three streams (each enqueued
+    while the previous ones run, as a pipelined caller does): every
     problem's output seeds, best trajectory and seed results are bitwise
     those of the batch run alone."""
     plan, probs, seeds = batchD["plan"], batchD["probs"], batchD["seeds"]
-    say("two batches on two streams")
+    say("three batches on three streams")
     ref = [torch.zeros_like(s) for s in seeds]
     plan.optimize([spec(p, seeds[i], 1200 + i, ref[i]) for i, p in enumerate(probs)])
     torch.cuda.synchronize()
-    outs = [[torch.zeros_like(s) for s in seeds] for _ in range(2)]
-    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    outs = [[torch.zeros_like(s) for s in seeds] for _ in range(3)]
+    streams = [torch.cuda.Stream() for _ in range(3)]
     torch.cuda.synchronize()   # the outputs' zero fill (default stream) is done
     for b, st in enumerate(streams):
         plan.optimize([spec(p, seeds[i], 1300 + 100 * b + i, outs[b][i])
@@ -175,7 +175,7 @@ def test_batches_on_two_streams_equal_one_at_a_time(batchD):
     for i, p in enumerate(probs):
         traj0, best0 = plan.get_best(1200 + i, p.T)
         r0 = plan.seed_results(1200 + i, p.S)
-        for b in range(2):
+        for b in range(3):
             tag = 1300 + 100 * b + i
             assert torch.equal(outs[b][i], ref[i]), (b, i)
             traj, best = plan.get_best(tag, p.T)
@@ -184,7 +184,7 @@ def test_batches_on_two_streams_equal_one_at_a_time(batchD):
             for k in r0:
                 assert np.array_equal(r[k], r0[k], equal_nan=r0[k].dtype.kind == "f"), (b, i, k)
     for i in range(len(probs)):
-        for tag in (1200 + i, 1300 + i, 1400 + i):
+        for tag in (1200 + i, 1300 + i, 1400 + i, 1500 + i):
             plan.release(tag)
 
 
