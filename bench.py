@@ -233,9 +233,9 @@ def run_batched(args, dsopt, torch, configs, params):
         st = streams[stepc[0] % len(streams)]
         stepc[0] += 1
         plan.optimize([dict(s, tag=base + i) for i, s in enumerate(specs)], stream=st)
-        if len(pending) >= max(1, args.batch_depth - 1):
-            read_back(pending.pop(0))
         pending.append(base)
+        while len(pending) >= max(1, args.batch_depth):
+            read_back(pending.pop(0))
 
     def drain():
         while pending:
